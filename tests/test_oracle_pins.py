@@ -1,0 +1,524 @@
+"""Pins for the FP64 oracle: every check compares it with something other than
+itself -- closed forms, symmetries, an independent equation-of-motion
+integration, textbook identities of the Kalman update, statistics that a
+consistent filter must satisfy, and finite differences.
+
+The paper prints no worked example or numeric result for the step (its
+throughput figures are not reproduced in the text and it states that the
+mini-apps carry no physics validation), so no printed value can serve as a
+pin; the checks below are chosen so that a dropped term, a wrong sign, a
+wrong index or a transposed operand in the oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import least_squares
+
+import oracle as O
+from paper_2409_09228_amd import synth as S
+
+B38 = 3.8
+b38 = S.C_LIGHT * B38
+
+
+def rand_tracks(rng, n, theta_lo=0.4, theta_hi=1.2, kmin=0.5, kmax=5.0):
+    sgn = np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    return np.stack([rng.normal(0, 0.3, n), rng.normal(0, 0.3, n), rng.normal(0, 0.3, n),
+                     sgn * rng.uniform(kmin, kmax, n), rng.uniform(-np.pi, np.pi, n),
+                     rng.uniform(theta_lo, theta_hi, n)], axis=1)
+
+
+# ------------------------------------------------------------------ propagation
+def _lorentz_rhs(k):
+    def f(state):
+        tt = state[3:]
+        return np.concatenate([tt, k * np.array([tt[1], -tt[0], 0.0])])
+    return f
+
+
+def _rk4_step(f, st, h):
+    k1 = f(st); k2 = f(st + 0.5 * h * k1); k3 = f(st + 0.5 * h * k2); k4 = f(st + h * k3)
+    return st + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+
+
+def _start_state(p, bz):
+    x, y, z, kap, phi, th = p
+    t = np.array([np.sin(th) * np.cos(phi), np.sin(th) * np.sin(phi), np.cos(th)])
+    return np.concatenate([[x, y, z], t]), S.C_LIGHT * bz * kap * np.sin(th)
+
+
+def rk4_track(p, bz, l_end, nstep):
+    """Integrate the Lorentz-force equation of motion over path length l.
+
+    d r/dl = t,  d t/dl = (0.0029979 Bz q/p) (t_y, -t_x, 0)  with q/p = kappa sin(theta).
+    Independent of the oracle's helix formula and curvature convention.
+    """
+    st, k = _start_state(p, bz)
+    f = _lorentz_rhs(k)
+    h = l_end / nstep
+    for _ in range(nstep):
+        st = _rk4_step(f, st, h)
+    return st
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_p2z_matches_lorentz_integration(seed):
+    rng = np.random.default_rng(seed)
+    p = rand_tracks(rng, 1)[0]
+    zk = p[2] + 40.0
+    po, F, fl = O.propagate(0, p, zk, B38)
+    assert fl == 0
+    l_end = (zk - p[2]) / np.cos(p[5])
+    st = rk4_track(p, B38, l_end, 4000)
+    np.testing.assert_allclose(po[:3], st[:3], atol=1e-9)
+    # direction: phi from the integrated tangent (mod 2 pi), theta unchanged
+    phi_rk = np.arctan2(st[4], st[3])
+    assert abs(np.angle(np.exp(1j * (po[4] - phi_rk)))) < 1e-9
+    assert po[5] == p[5] and po[3] == p[3]
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_p2r_first_crossing_matches_lorentz_integration(seed):
+    rng = np.random.default_rng(seed)
+    p = rand_tracks(rng, 1, 0.5, 2.6, 0.3, 1.0)[0]
+    p[:3] = [0.01, -0.02, 0.0]
+    rk = 30.0
+    po, F, fl = O.propagate(1, p, rk, B38)
+    assert fl == 0
+    # march the integrated trajectory until it first reaches r = rk, then bisect the last step
+    st, k = _start_state(p, B38)
+    f = _lorentz_rhs(k)
+    h = 0.01
+    while True:
+        nxt = _rk4_step(f, st, h)
+        if np.hypot(nxt[0], nxt[1]) >= rk:
+            break
+        st = nxt
+    lo, hi = 0.0, h
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        sm = _rk4_step(f, st, mid)
+        if np.hypot(sm[0], sm[1]) < rk:
+            lo = mid
+        else:
+            hi = mid
+    sm = _rk4_step(f, st, 0.5 * (lo + hi))
+    np.testing.assert_allclose(po[:3], sm[:3], atol=1e-7)
+    assert abs(np.hypot(po[0], po[1]) - rk) < 1e-10
+
+
+def test_zero_field_is_straight_line():
+    rng = np.random.default_rng(5)
+    for p in rand_tracks(rng, 5):
+        zk = p[2] + 25.0
+        po, F, fl = O.propagate(0, p, zk, 0.0)
+        s = (zk - p[2]) * np.tan(p[5])
+        np.testing.assert_allclose(po, [p[0] + s * np.cos(p[4]), p[1] + s * np.sin(p[4]), zk,
+                                        p[3], p[4], p[5]], rtol=0, atol=1e-12)
+        # cylinder: the line's exit point from a circle of radius 20 cm
+        po, F, fl = O.propagate(1, p, 20.0, 0.0)
+        d = np.array([np.cos(p[4]), np.sin(p[4])])
+        x0 = p[:2]
+        bb = x0 @ d
+        s = -bb + np.sqrt(bb * bb - x0 @ x0 + 400.0)
+        np.testing.assert_allclose(po[:2], x0 + s * d, atol=1e-12)
+        np.testing.assert_allclose(po[2], p[2] + s / np.tan(p[5]), atol=1e-12)
+
+
+def test_small_curvature_approaches_line():
+    p = np.array([0.1, -0.2, 0.3, 1e-7, 0.7, 0.9])
+    po, F, _ = O.propagate(0, p, 60.0, B38)
+    s = (60.0 - 0.3) * np.tan(0.9)
+    line = [0.1 + s * np.cos(0.7), -0.2 + s * np.sin(0.7)]
+    # sagitta ~ omega s^2 / 2 = 1.1e-9 * s^2 / 2
+    assert np.max(np.abs(po[:2] - line)) < 2e-9 * s * s
+    assert np.max(np.abs(po[:2] - line)) > 1e-11
+
+
+def test_full_turn_returns_to_start():
+    p = np.array([0.3, -0.1, 0.0, 2.0, 1.1, 0.8])
+    om = -b38 * p[3]
+    s = 2 * np.pi / abs(om)
+    zk = p[2] + s / np.tan(p[5])
+    po, _, _ = O.propagate(0, p, zk, B38)
+    np.testing.assert_allclose(po[:2], p[:2], atol=1e-10)
+    assert abs(po[4] - (p[4] + 2 * np.pi * np.sign(om))) < 1e-10
+
+
+@pytest.mark.parametrize("geom,t1,t2", [(0, 20.0, 45.0), (1, 15.0, 40.0)])
+def test_composition_and_chain_rule(geom, t1, t2):
+    rng = np.random.default_rng(7)
+    if geom == 0:
+        ps = rand_tracks(rng, 4)
+    else:
+        ps = rand_tracks(rng, 4, 0.5, 2.6, 0.3, 1.0)
+        ps[:, :3] = 0.01
+    for p in ps:
+        a, Fa, fa = O.propagate(geom, p, t1, B38)
+        b2, Fb, fb = O.propagate(geom, a, t2, B38)
+        c, Fc, fc = O.propagate(geom, p, t2, B38)
+        assert fa == fb == fc == 0
+        np.testing.assert_allclose(b2, c, rtol=1e-12, atol=1e-10)
+        np.testing.assert_allclose(Fb @ Fa, Fc, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("geom", [0, 1])
+def test_mirror_symmetry(geom):
+    M = np.diag([1.0, -1.0, 1.0, -1.0, -1.0, 1.0])
+    rng = np.random.default_rng(8)
+    for p in rand_tracks(rng, 4, 0.5, 1.2, 0.3, 2.0):
+        if geom == 1:
+            p[:3] = [0.01, 0.02, 0.0]
+        t = 35.0 if geom == 0 else 25.0
+        a, Fa, _ = O.propagate(geom, p, t, B38)
+        b2, Fb, _ = O.propagate(geom, M @ p, t, B38)
+        np.testing.assert_allclose(b2, M @ a, atol=1e-10)
+        np.testing.assert_allclose(Fb, M @ Fa @ M, atol=1e-9)
+
+
+@pytest.mark.parametrize("geom", [0, 1])
+def test_rotation_invariance_about_z(geom):
+    rng = np.random.default_rng(9)
+    al = 0.83
+    J = np.eye(6)
+    J[:2, :2] = [[np.cos(al), -np.sin(al)], [np.sin(al), np.cos(al)]]
+    for p in rand_tracks(rng, 4, 0.5, 1.2, 0.3, 2.0):
+        if geom == 1:
+            p[:3] = [0.01, 0.02, 0.0]
+        t = 35.0 if geom == 0 else 25.0
+        a, Fa, _ = O.propagate(geom, p, t, B38)
+        q = J @ p
+        q[4] += al
+        b2, Fb, _ = O.propagate(geom, q, t, B38)
+        ar = J @ a
+        ar[4] += al
+        np.testing.assert_allclose(b2, ar, atol=1e-10)
+        np.testing.assert_allclose(Fb, J @ Fa @ J.T, atol=1e-9)
+
+
+@pytest.mark.parametrize("geom", [0, 1])
+def test_jacobian_matches_central_differences(geom):
+    rng = np.random.default_rng(10)
+    ps = rand_tracks(rng, 5, 0.5, 1.2, 0.3, 5.0)
+    if geom == 1:
+        ps[:, :3] = rng.normal(0, 0.01, (5, 3))
+    t = 50.0 if geom == 0 else 30.0
+    for p in ps:
+        _, F, fl = O.propagate(geom, p, t, B38)
+        if fl:
+            continue
+        Fd = np.zeros((6, 6))
+        for j in range(6):
+            h = 1e-6
+            e = np.zeros(6); e[j] = h
+            Fd[:, j] = (O.propagate(geom, p + e, t, B38)[0] - O.propagate(geom, p - e, t, B38)[0]) / (2 * h)
+        np.testing.assert_allclose(F, Fd, rtol=1e-6, atol=5e-6)
+
+
+def test_p2z_zero_z_row_and_p2r_zero_radial_row():
+    rng = np.random.default_rng(11)
+    for p in rand_tracks(rng, 5):
+        po, F, _ = O.propagate(0, p, 60.0, B38)
+        assert np.max(np.abs(F[2])) < 1e-13
+    for p in rand_tracks(rng, 5, 0.5, 2.6, 0.3, 1.0):
+        p[:3] = 0.01
+        po, F, _ = O.propagate(1, p, 30.0, B38)
+        radial = (po[0] * F[0] + po[1] * F[1]) / np.hypot(po[0], po[1])
+        assert np.all(np.abs(radial) < 1e-11 * (np.abs(F[0]) + np.abs(F[1]) + 1.0))
+
+
+def test_truth_crossings_agree_with_generator_geometry():
+    """The generator's circle-centre construction (independent code) and the
+    oracle's propagation give the same crossing points."""
+    s = S.generate("p2z_1x8192")
+    for k in (0, 7, 19):
+        pts = S.truth_cross_plane(s["truth"][:50], s["layer_z"][k], s["bz"])
+        for i in range(50):
+            po, _, _ = O.propagate(0, s["truth"][i], s["layer_z"][k], s["bz"])
+            np.testing.assert_allclose(po[:3], pts[i], atol=1e-9)
+    r = S.generate("p2r_100x9600", n_events=1)
+    sel = np.nonzero(r["nlay"] == 20)[0][:40]
+    for k in (0, 9, 19):
+        pts = S.truth_cross_cylinder(r["truth"][sel], r["layer_r"][k], r["bz"])
+        for j, i in enumerate(sel):
+            po, _, fl = O.propagate(1, r["truth"][i], r["layer_r"][k], r["bz"])
+            assert fl == 0
+            np.testing.assert_allclose(po[:3], pts[j], atol=1e-8)
+
+
+def test_unreachable_cylinder_flag():
+    p = np.array([0.0, 0.0, 0.0, 4.0, 0.3, 1.0])   # R = 1/(b*4) = 21.9 cm: max radius 43.9 cm
+    _, _, fl = O.propagate(1, p, 43.0, B38)
+    assert fl == 0
+    po, _, fl = O.propagate(1, p, 44.5, B38)
+    assert fl == O.ST_NO_CROSSING
+    np.testing.assert_array_equal(po, p)
+
+
+# ------------------------------------------------------------------ update
+def rand_spd(rng, n, scale):
+    A = rng.normal(0, 1, (n, n))
+    return scale * (A @ A.T + n * np.eye(n)) / n
+
+
+def test_update_equals_information_form():
+    rng = np.random.default_rng(12)
+    H = np.hstack([np.eye(3), np.zeros((3, 3))])
+    for _ in range(10):
+        P = rand_spd(rng, 6, 1e-2)
+        V = rand_spd(rng, 3, 1e-3)
+        x = rng.normal(0, 1, 6)
+        m = x[:3] + rng.normal(0, 0.05, 3)
+        po, Po, chi2, fl = O.update(x, O.pack_sym(P), m, O.pack_sym(V))
+        assert fl == 0
+        Pinv = np.linalg.inv(P)
+        Vinv = np.linalg.inv(V)
+        Pi = np.linalg.inv(Pinv + H.T @ Vinv @ H)
+        xi = Pi @ (Pinv @ x + H.T @ Vinv @ m)
+        np.testing.assert_allclose(po, xi, rtol=1e-10, atol=1e-12)
+        np.testing.assert_allclose(O.unpack_sym(Po), Pi, rtol=1e-9, atol=1e-14)
+        # chi2 is the minimum of the MAP objective
+        jmin = (xi - x) @ Pinv @ (xi - x) + (m - H @ xi) @ Vinv @ (m - H @ xi)
+        assert abs(chi2 - jmin) < 1e-9 * max(1.0, jmin)
+
+
+def test_update_infinite_prior_collapses_to_hit():
+    """A huge prior variance: the state moves onto the hit and the position
+    covariance becomes V (to relative order V/P).  The plain form loses about
+    eps*P to cancellation, the Joseph form does not."""
+    rng = np.random.default_rng(13)
+    V = rand_spd(rng, 3, 1e-4)
+    x = rng.normal(0, 1, 6)
+    m = rng.normal(0, 1, 3)
+    for scale, joseph in ((1e4, False), (1e8, True)):
+        P = np.eye(6) * scale
+        po, Po, chi2, fl = O.update(x, O.pack_sym(P), m, O.pack_sym(V), joseph=joseph)
+        rel = np.abs(V).max() / scale  # the update keeps a fraction ~V/P of the residual
+        np.testing.assert_allclose(po[:3], m, atol=10 * rel * np.abs(m - x[:3]).max() + 1e-12)
+        cancel = 1e-14 if joseph else 20 * np.finfo(float).eps * scale
+        np.testing.assert_allclose(O.unpack_sym(Po)[:3, :3], V, rtol=1e-6, atol=cancel)
+        assert abs(chi2 * scale / np.sum((m - x[:3]) ** 2) - 1.0) < 1e-3  # S ~ scale * I
+
+
+def test_update_zero_residual_keeps_state():
+    rng = np.random.default_rng(14)
+    P = rand_spd(rng, 6, 1e-2)
+    V = rand_spd(rng, 3, 1e-3)
+    x = rng.normal(0, 1, 6)
+    po, Po, chi2, _ = O.update(x, O.pack_sym(P), x[:3], O.pack_sym(V))
+    np.testing.assert_allclose(po, x, atol=1e-15)
+    assert chi2 == 0.0
+
+
+def test_joseph_equals_plain_and_covariance_spd():
+    rng = np.random.default_rng(15)
+    for _ in range(10):
+        P = rand_spd(rng, 6, 1e-2)
+        V = rand_spd(rng, 3, 1e-3)
+        x = rng.normal(0, 1, 6)
+        m = x[:3] + 0.01
+        a = O.update(x, O.pack_sym(P), m, O.pack_sym(V), joseph=False)
+        j = O.update(x, O.pack_sym(P), m, O.pack_sym(V), joseph=True)
+        np.testing.assert_allclose(a[0], j[0], rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(a[1], j[1], rtol=1e-9, atol=1e-15)
+        Pn = O.unpack_sym(j[1])
+        assert np.all(np.linalg.eigvalsh(Pn) > 0)
+        assert np.all(np.linalg.eigvalsh(Pn) <= np.linalg.eigvalsh(P).max() + 1e-15)
+
+
+def test_update_not_pd_flag():
+    P = np.eye(6) * 1e-4
+    V = -2e-4 * np.eye(3)
+    po, Po, chi2, fl = O.update(np.zeros(6), O.pack_sym(P), np.ones(3), O.pack_sym(V))
+    assert fl == O.ST_NOT_PD
+
+
+# ------------------------------------------------------------------ chain
+def test_noise_free_hits_reproduce_truth():
+    s = S.generate("p2z_1x8192")
+    n = 256
+    sub = S.subset(s, np.arange(n))
+    sub["par"] = sub["truth"].copy()
+    sub["hit_pos"] = np.stack([S.truth_cross_plane(sub["truth"], z, s["bz"]) for z in s["layer_z"]])
+    po, co, chi2, st = O.run_sample(sub)
+    assert np.all(st == 20 << 16)
+    last = S.truth_cross_plane(sub["truth"], s["layer_z"][-1], s["bz"])
+    np.testing.assert_allclose(po[:, :3], last, atol=1e-9)
+    np.testing.assert_allclose(po[:, 3], sub["truth"][:, 3], atol=1e-10)
+    np.testing.assert_allclose(po[:, 5], sub["truth"][:, 5], atol=1e-12)
+    assert chi2.max() < 1e-12
+
+
+def test_chi2_and_pulls_are_consistent_p2z():
+    s = S.generate("p2z_1x8192")
+    po, co, chi2, st = O.run_sample(s)
+    assert np.all(st == 20 << 16)
+    assert 0.97 < chi2.mean() / 60.0 < 1.03
+    last = S.truth_cross_plane(s["truth"], s["layer_z"][-1], s["bz"])
+    P = O.unpack_sym(co)
+    for i in (0, 1):
+        pull = (po[:, i] - last[:, i]) / np.sqrt(P[:, i, i])
+        assert abs(pull.mean()) < 0.05 and 0.97 < pull.std() < 1.03
+    for i in (3, 5):
+        pull = (po[:, i] - s["truth"][:, i]) / np.sqrt(P[:, i, i])
+        assert abs(pull.mean()) < 0.05 and 0.96 < pull.std() < 1.04
+
+
+def test_chi2_consistent_p2r():
+    """Barrel hits carry no radial noise while V is isotropic, and the
+    propagated covariance has an exactly null radial direction: E[chi2] per
+    layer is 2, not 3."""
+    r = S.generate("p2r_100x9600", n_events=1)
+    po, co, chi2, st = O.run_sample(r)
+    assert np.all(st == r["nlay"] << 16)
+    assert 0.97 < chi2.sum() / (2.0 * r["nlay"].sum()) < 1.03
+
+
+def _line_map(q, layers_z):
+    """Straight-line (zero field) model of the hits: positions on planes z_k."""
+    x0, y0, z0, _, phi, th = q
+    s = (layers_z - z0) * np.tan(th)
+    return np.stack([x0 + s * np.cos(phi), y0 + s * np.sin(phi), layers_z], axis=1)
+
+
+@pytest.mark.slow
+def test_zero_field_filter_agrees_with_weighted_least_squares():
+    """At Bz = 0 the filter's final estimate equals the batch weighted
+    least-squares (MAP) line fit with the seed as prior, up to terms of second
+    order in the noise (the parameterisation is non-linear in the angles):
+    halving every sigma shrinks the difference about four-fold."""
+    rng = np.random.default_rng(16)
+    L = 10
+    lz = S.layer_table(0, L)
+    truth = np.array([0.01, -0.01, 0.0, 1.0, 0.4, 0.9])
+    e_seed = rng.normal(0, 1, 6)
+    e_hit = rng.normal(0, 1, (L, 3))
+    diffs = []
+    for sig in (0.02, 0.01, 0.005):
+        seed = truth + sig * e_seed
+        C0 = sig * sig * np.eye(6)
+        V = sig * sig * np.eye(3)
+        hits = _line_map(truth, lz) + sig * e_hit
+        po, co, chi2, st = O.run(0, seed[None], O.pack_sym(C0)[None], hits[:, None, :],
+                                 np.broadcast_to(O.pack_sym(V), (L, 1, 6)).copy(), lz, 0.0)
+        W0 = np.linalg.cholesky(np.linalg.inv(C0)).T
+        Wv = np.linalg.cholesky(np.linalg.inv(V)).T
+
+        def res(q):
+            return np.concatenate([W0 @ (q - seed), ((hits - _line_map(q, lz)) @ Wv.T).ravel()])
+
+        q = least_squares(res, seed, xtol=1e-15, ftol=1e-15, gtol=1e-15).x
+        end = _line_map(q, lz[-1:])[0]
+        fit = np.array([end[0], end[1], q[4], q[5]])
+        ekf = po[0, [0, 1, 4, 5]]
+        diffs.append(np.max(np.abs(fit - ekf)))
+        assert diffs[-1] < 5.0 * sig * sig
+    assert 3.5 < diffs[0] / diffs[1] < 4.5 and 3.5 < diffs[1] / diffs[2] < 4.5
+
+
+def test_status_semantics():
+    s = S.generate("p2z_1x8192")
+    sub = S.subset(s, np.arange(8))
+    # NaN hit on layer 5 of track 2; non-positive-definite S on layer 9 of track 4
+    sub["hit_pos"] = sub["hit_pos"].copy()
+    sub["hit_cov"] = sub["hit_cov"].copy()
+    sub["hit_pos"][5, 2, 1] = np.nan
+    sub["hit_cov"][9, 4] = O.pack_sym(-np.eye(3))
+    sub["par"] = sub["par"].copy()
+    sub["par"][6, 3] = np.inf
+    sub["nlay"] = sub["nlay"].copy()
+    sub["nlay"][7] = 0
+    po, co, chi2, st = O.run_sample(sub)
+    assert st[2] == (O.ST_NONFINITE | (5 << 16))
+    assert st[4] == (O.ST_NOT_PD | (9 << 16))
+    assert st[6] == O.ST_NONFINITE
+    assert st[7] == 0 and chi2[7] == 0.0
+    np.testing.assert_array_equal(po[7], sub["par"][7])
+    np.testing.assert_array_equal(po[6], sub["par"][6])
+    for i, k in ((2, 5), (4, 9)):
+        nl = sub["nlay"].copy()
+        nl[i] = k
+        q = dict(sub, nlay=nl)
+        po2, co2, chi22, st2 = O.run_sample(q)
+        np.testing.assert_array_equal(po[i], po2[i])
+        np.testing.assert_array_equal(co[i], co2[i])
+        assert chi2[i] == chi22[i]
+    for i in (0, 1, 3, 5):
+        assert st[i] == 20 << 16
+
+
+def test_p2r_freezes_at_unreachable_layer():
+    """Truth seed and exact hits: the filter follows the true helix and stops
+    with the no-crossing flag at the first cylinder beyond its largest radius."""
+    r = S.generate("p2r_100x9600", n_events=1)
+    idx = np.nonzero(r["nlay"] < 8)[0][:5]
+    sub = S.subset(r, idx)
+    sub["par"] = sub["truth"].copy()
+    pts = np.stack([S.truth_cross_cylinder(sub["truth"], rk, r["bz"]) for rk in r["layer_r"]])
+    sub["hit_pos"] = np.where(np.isfinite(pts), pts, 0.0)
+    sub["nlay"] = np.full(len(idx), 20, np.int32)
+    po, co, chi2, st = O.run_sample(sub)
+    rmax = S.truth_max_radius(sub["truth"], r["bz"])
+    expect = np.sum(r["layer_r"][None, :] < rmax[:, None], axis=1)
+    np.testing.assert_array_equal(st & 0xFF, O.ST_NO_CROSSING)
+    np.testing.assert_array_equal(st >> 16, expect)
+    assert chi2.max() < 1e-12
+
+
+# ------------------------------------------------------------------ gradient
+def _fd_grad(geom, sub, h=1e-4):
+    layers = sub["layer_z"] if geom == 0 else sub["layer_r"]
+    n = sub["par"].shape[0]
+    L = sub["hit_pos"].shape[0]
+    gp = np.zeros((n, 6))
+    gh = np.zeros((L, n, 3))
+
+    def chi(par, hits):
+        return O.run(geom, par, sub["cov"], hits, sub["hit_cov"], layers, sub["bz"], nlay=sub["nlay"])[2]
+
+    for a in range(6):
+        e = np.zeros_like(sub["par"]); e[:, a] = h
+        gp[:, a] = (chi(sub["par"] + e, sub["hit_pos"]) - chi(sub["par"] - e, sub["hit_pos"])) / (2 * h)
+    for k in range(L):
+        for a in range(3):
+            e = np.zeros_like(sub["hit_pos"]); e[k, :, a] = h
+            gh[k, :, a] = (chi(sub["par"], sub["hit_pos"] + e) - chi(sub["par"], sub["hit_pos"] - e)) / (2 * h)
+    return gh, gp
+
+
+@pytest.mark.parametrize("name", ["p2z_1x8192", "p2r_100x9600"])
+def test_reference_gradient_matches_finite_differences(name):
+    s = S.generate(name, n_events=1)
+    geom = int(s["geom"][0])
+    idx = np.nonzero(s["nlay"] >= 6)[0][:4]
+    sub = S.subset(s, idx)
+    sub["hit_pos"] = sub["hit_pos"][:8]
+    sub["hit_cov"] = sub["hit_cov"][:8]
+    sub["nlay"] = np.minimum(sub["nlay"], 8)
+    layers = sub["layer_z"] if geom == 0 else sub["layer_r"]
+    gh, gp = O.grad_chi2(geom, sub["par"], sub["cov"], sub["hit_pos"], sub["hit_cov"], layers,
+                         sub["bz"], nlay=sub["nlay"])
+    # Richardson-extrapolated central differences: truncation error O(h^4)
+    f1h, f1p = _fd_grad(geom, sub, 1e-4)
+    f2h, f2p = _fd_grad(geom, sub, 5e-5)
+    fh, fp = (4 * f2h - f1h) / 3, (4 * f2p - f1p) / 3
+    scale_h = np.abs(fh).max()
+    scale_p = np.abs(fp).max(axis=0)
+    assert np.max(np.abs(gh - fh)) < 1e-6 * scale_h
+    assert np.all(np.abs(gp - fp) <= 1e-6 * scale_p + 1e-6)
+
+
+def test_last_layer_gradient_closed_form():
+    """Nothing downstream depends on the last hit: d chi2 / d m_L = 2 S_L^-1 r_L."""
+    s = S.generate("p2z_1x8192")
+    sub = S.subset(s, np.arange(6))
+    L = sub["hit_pos"].shape[0]
+    gh, gp = O.grad_chi2(0, sub["par"], sub["cov"], sub["hit_pos"], sub["hit_cov"], sub["layer_z"], sub["bz"])
+    nl = np.full(6, L - 1, np.int32)
+    po, co, _, _ = O.run(0, sub["par"], sub["cov"], sub["hit_pos"], sub["hit_cov"], sub["layer_z"],
+                         sub["bz"], nlay=nl)
+    for i in range(6):
+        pt, F, _ = O.propagate(0, po[i], sub["layer_z"][-1], sub["bz"])
+        Pt = F @ O.unpack_sym(co[i]) @ F.T
+        Sm = Pt[:3, :3] + O.unpack_sym(sub["hit_cov"][-1, i])
+        r = sub["hit_pos"][-1, i] - pt[:3]
+        np.testing.assert_allclose(gh[-1, i], 2 * np.linalg.solve(Sm, r), rtol=1e-8)

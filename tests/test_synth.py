@@ -1,0 +1,54 @@
+"""The synthetic workloads: determinism, shapes and distributions."""
+import numpy as np
+
+from paper_2409_09228_amd import synth as S
+
+
+def test_deterministic_and_prefix_stable():
+    a = S.generate("p2z_100x9600", n_events=2)
+    b = S.generate("p2z_100x9600", n_events=2)
+    for k in ("par", "cov", "hit_pos", "hit_cov", "nlay", "truth"):
+        np.testing.assert_array_equal(a[k], b[k])
+    c = S.generate("p2z_100x9600", n_events=1)
+    np.testing.assert_array_equal(c["par"], a["par"][:9600])
+    np.testing.assert_array_equal(c["hit_pos"], a["hit_pos"][:, :9600])
+
+
+def test_p2z_distributions():
+    s = S.generate("p2z_1x8192")
+    t = s["truth"]
+    assert t.shape == (8192, 6) and s["hit_pos"].shape == (20, 8192, 3)
+    k = np.abs(t[:, 3])
+    assert k.min() >= 0.5 and k.max() <= 5.0
+    assert 0.45 < np.mean(t[:, 3] > 0) < 0.55
+    assert t[:, 5].min() >= 0.4 and t[:, 5].max() <= 1.2
+    assert abs(np.std(s["par"][:, 0] - t[:, 0]) - 0.01) < 5e-4
+    np.testing.assert_allclose(s["layer_z"], 10 + 5 * np.arange(20))
+    # hits lie within a few sigma of their planes
+    dz = s["hit_pos"][:, :, 2] - s["layer_z"][:, None]
+    assert abs(dz.std() - 0.01) < 3e-4
+    assert np.all(s["nlay"] == 20)
+
+
+def test_p2r_hits_on_cylinders_and_reachability():
+    r = S.generate("p2r_100x9600", n_events=1)
+    rr = np.hypot(r["hit_pos"][..., 0], r["hit_pos"][..., 1])
+    k = np.arange(20)[:, None]
+    valid = k < r["nlay"][None, :]
+    np.testing.assert_allclose(rr[valid], np.broadcast_to(r["layer_r"][:, None], rr.shape)[valid], rtol=1e-12)
+    assert 12.0 < r["nlay"].mean() < 13.6
+    rmax = S.truth_max_radius(r["truth"], r["bz"])
+    last = r["layer_r"][np.maximum(r["nlay"] - 1, 0)]
+    assert np.all(last <= 0.9 * rmax + 1e-9)
+
+
+def test_uneven_mix():
+    u = S.generate("uneven_250k")
+    assert u["par"].shape[0] == 250000
+    assert np.sum(u["geom"] == 0) == 125000
+    z = u["nlay"][u["geom"] == 0]
+    assert z.min() == 5 and z.max() == 30
+    assert 17.0 < z.mean() < 18.0
+    hp, hc, off = S.to_ragged(u["hit_pos"][:, :100], u["hit_cov"][:, :100], u["nlay"][:100])
+    assert hp.shape[0] == u["nlay"][:100].sum()
+    np.testing.assert_array_equal(hp[off[7] + 3], u["hit_pos"][3, 7])
