@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the batched Kalman-filter step on one MI355X.
+
+One step = one launch of the whole step (propagate + Kalman update through
+every layer of every track) over the 100-event x 9600-track plane sample
+(960,000 tracks x 20 planes = 19.2M track-layer updates), inputs resident in
+HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--layout soa|aosoaB]
+                    [--flags 0|1|3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "track-layer updates/sec (propagate+Kalman) FP32 at 1 GPU; % of HBM/VALU roofline"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+# Algorithmic cost of one track-layer update (counted from the method's
+# formulation, FMA = 2 flops, each sin/cos/reciprocal/sqrt = 1 flop; the
+# derivation is listed operation by operation in the design doc).
+FLOPS_PER_UPDATE = {0: 421.0, 1: 711.0}
+# Bytes that must move per track (parameters + covariance in and out, chi2,
+# status) and per layer (hit position + hit covariance), float32.
+TRACK_BYTES = (6 + 21) * 4 * 2 + 4 + 4
+LAYER_BYTES = (3 + 6) * 4
+
+
+def parse_layout(s: str):
+    from paper_2409_09228_amd import kf as K
+    if s == "soa":
+        return K.SOA
+    if s.startswith("aosoa"):
+        return K.aosoa(int(s[5:]))
+    raise SystemExit(f"unknown layout {s}")
+
+
+def cpu_baseline(sample, n_tracks: int):
+    """The FP64 oracle on the first n_tracks of the same sample, all host cores."""
+    import oracle as O
+    from paper_2409_09228_amd import synth as S
+    idx = np.arange(min(n_tracks, sample["par"].shape[0]))
+    sub = S.subset(sample, idx)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    O.run_sample(sub, nthreads=threads)
+    dt = time.perf_counter() - t0
+    upd = int(sub["nlay"].sum())
+    return {"value": upd / dt, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {len(idx)} tracks ({upd} track-layer updates) of the same sample, "
+                      f"FP64, OpenMP over tracks, {dt:.2f} s wall"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="p2z_100x9600")
+    ap.add_argument("--layout", default="soa")
+    ap.add_argument("--flags", type=int, default=0)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--tpt", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-tracks", type=int, default=480000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB device buffer --steps times (calibrates the HBM byte counters)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the step has no cross-GPU work and this build runs on a "
+              "single MI355X; run it with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2409_09228_amd import kf as K
+    from paper_2409_09228_amd import synth as S
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_call": src.numel() * 4,
+                          "copy_probe_bytes_written_per_call": dst.numel() * 4, "calls": args.steps}))
+        return 0
+    K.lib()
+    layout = parse_layout(args.layout)
+    sample = S.generate(args.workload)
+    if sample["geom"].min() != sample["geom"].max():
+        raise SystemExit("bench.py times single-geometry workloads")
+    geom = int(sample["geom"][0])
+    st = K.stage_sample(sample, layout)
+    n = st["n"]
+    updates = int(sample["nlay"].sum())
+    par_out = torch.empty_like(st["par"])
+    cov_out = torch.empty_like(st["cov"])
+    chi2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    tune = (args.block, args.tpt)
+    stream = torch.cuda.current_stream()
+
+    step_prealloc = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                                   st["bz"], n, out=(par_out, cov_out), chi2=chi2, status=status,
+                                   nlay=st["nlay"], layout=layout, flags=args.flags, tune=tune, stream=stream)
+
+    # warm-up: W steps, and at least 300 ms of GPU work so that clocks have
+    # settled before the timed region
+    for _ in range(args.warmup):
+        step_prealloc()
+    torch.cuda.synchronize()
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < 0.3:
+        for _ in range(20):
+            step_prealloc()
+        torch.cuda.synchronize()
+    ok = int(((status & 0xFF) == 0).sum().item())
+    # timed region: K launches with an event after each on the launch stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for j in range(args.steps):
+        step_prealloc()
+        ev[j + 1].record(stream)
+    ev[-1].synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[j].elapsed_time(ev[j + 1]) for j in range(args.steps)]
+    ms = ev[0].elapsed_time(ev[-1])
+    ms_step = ms / args.steps
+    value = updates * args.steps / (ms / 1e3)
+    kernel_ms = sum(per) / len(per)  # average launch duration over the timed region
+    per.sort()
+
+    flops = FLOPS_PER_UPDATE[geom] * updates
+    bytes_ = TRACK_BYTES * n + LAYER_BYTES * updates
+    sec = kernel_ms / 1e3
+    hbm = bytes_ / sec / 1e9
+    tfl = flops / sec / 1e12
+    fr_hbm = hbm / HBM_PEAK_GBS
+    fr_alu = tfl / FP32_PEAK_TFLOPS
+    if fr_hbm >= fr_alu:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(fr_hbm, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(fr_alu, 4)}
+    roof["traffic"] = None
+    roof["alu_frac_fp32_published"] = round(fr_alu, 4)
+    roof["hbm_frac"] = round(fr_hbm, 4)
+    roof["kernel"] = "kf_step_kernel<%d,%d>" % (geom, {0: 0, 1: 1, 3: 2}.get(args.flags, 0))
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "track-layer updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.flags == 0 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "tracks": n, "layers": int(sample["hit_pos"].shape[0]),
+                   "updates_per_step": updates, "layout": args.layout, "precision_flags": args.flags,
+                   "block": args.block, "tracks_per_thread": args.tpt,
+                   "tracks_per_s": round(n * args.steps / (ms / 1e3), 1), "ok_tracks": ok,
+                   "host_wall_s": round(wall, 4), "launch_ms_mean": round(kernel_ms, 4),
+                   "launch_ms_median": round(per[len(per) // 2], 4),
+                   "launch_ms_min": round(per[0], 4), "launch_ms_max": round(per[-1], 4)},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_tracks)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,184 @@
+/*
+ * kf.h -- C ABI of libkf.so, a batched Kalman-filter step for charged-particle
+ * tracks on AMD Instinct MI355X (gfx950).
+ *
+ * The step is the one the p2z / p2r tracking mini-apps time (arXiv 2409.09228,
+ * Sec. 3 "Description of algorithm" and Sec. 3.2 "Computations and data
+ * structure"): for every track, propagate the helix from its current state to
+ * the next detector layer -- an endcap plane at fixed z ("propagate to z") or a
+ * barrel cylinder at fixed radius r ("propagate to r") -- carrying the 6x6
+ * covariance along with the propagation Jacobian F (C -> F C F^T), then update
+ * state and covariance with the single hit on that layer (3 coordinates and a
+ * 3x3 covariance), and repeat over the track's layers (Sec. 3.1, one hit per
+ * layer).
+ *
+ * Conventions shared by every entry point
+ *   Units: cm, GeV, tesla, rad.
+ *   Track parameters p = (x, y, z, kappa = q/pT [1/GeV], phi, theta), where phi
+ *   is the transverse direction angle and theta the polar angle.  The
+ *   transverse curvature is omega = -0.00299792458 * Bz * kappa [1/cm]
+ *   (d phi / ds = omega along the transverse arc length s).
+ *   Covariances are symmetric and stored as packed lower triangles, row-major:
+ *   element (i, j) with i >= j is number i*(i+1)/2 + j.  Track covariance: 21
+ *   numbers; hit covariance: 6 (xx, yx, yy, zx, zy, zz).
+ *   The hit measures global (x, y, z): H = [I3 | 0].  No process noise.
+ *
+ * Memory
+ *   Every array argument is DEVICE memory (hipMalloc'd or a torch CUDA tensor)
+ *   unless its comment says HOST.  Buffers are owned by the caller; the library
+ *   keeps no pointer after the call returns (work already enqueued aside) and
+ *   allocates nothing except where a function says so.  All calls enqueue on
+ *   `stream` (a hipStream_t; NULL = the null stream) and return without
+ *   synchronising.  Outputs may alias the matching inputs exactly (in-place);
+ *   any other overlap is undefined.  Float arrays must be 4-byte aligned.
+ *
+ * Track layouts (kf_layout_t), n = n_tracks, element e of track i:
+ *   KF_SOA           per-track arrays with e elements per track are stored
+ *                    element-major: offset e*n + i.
+ *   KF_AOSOA, B      blocks of B tracks (B in {16, 32, 64, 128, 256}):
+ *                    offset (i/B)*(E*B) + e*B + i%B for an array of E
+ *                    elements per track; the buffer holds ceil(n/B) blocks
+ *                    and the padding slots of the last block are neither read
+ *                    nor written.
+ *   Per-layer arrays (hits, checkpoints) add the layer l (0 <= l < n_layers):
+ *     KF_SOA          offset (l*E + e)*n + i
+ *     KF_AOSOA, B     offset ((i/B)*n_layers + l)*(E*B) + e*B + i%B
+ *   This is the array-of-structures-of-arrays organisation of Sec. 3.2 with a
+ *   free batch width B.
+ *
+ * Errors
+ *   Argument problems are reported synchronously through kf_status_t before
+ *   anything is enqueued; no exception crosses the ABI.  Numerical trouble of
+ *   one track is reported in its status word (below); that track stops at the
+ *   failing layer and keeps the state it had before it.
+ */
+#ifndef KF_H
+#define KF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KF_ABI_VERSION 1
+#define KF_MAX_LAYERS 64
+
+typedef enum {
+  KF_OK = 0,
+  KF_E_NULL = 1,      /* a required pointer is NULL */
+  KF_E_SHAPE = 2,     /* n_tracks < 0, n_layers outside [0, KF_MAX_LAYERS], ... */
+  KF_E_LAYOUT = 3,    /* unknown layout kind or block width */
+  KF_E_ALIGN = 4,     /* a float pointer is not 4-byte aligned */
+  KF_E_DEVICE = 5,    /* no usable gfx950 device */
+  KF_E_LAUNCH = 6,    /* the HIP runtime refused the launch */
+  KF_E_WORKSPACE = 7, /* workspace missing or too small */
+  KF_E_FLAGS = 8,     /* unknown flag bits or tuning values */
+  KF_E_UNSUPPORTED = 9 /* valid request this build does not implement */
+} kf_status_t;
+
+enum { KF_SOA = 0, KF_AOSOA = 1 };
+typedef struct {
+  int32_t kind;  /* KF_SOA or KF_AOSOA */
+  int32_t block; /* AoSoA block width B; ignored for KF_SOA */
+} kf_layout_t;
+
+/* Launch shape; pass NULL for the built-in default.  block_threads in
+ * {64, 128, 256}; tracks_per_thread in {1, 2} (a thread carries that many
+ * tracks through the layer loop together). */
+typedef struct {
+  int32_t block_threads;
+  int32_t tracks_per_thread;
+} kf_tune_t;
+
+/* flags */
+enum {
+  KF_F_FP64_INVERSE = 1u << 0, /* S = H P H^T + V, S^-1 and the gain K in FP64 */
+  KF_F_JOSEPH = 1u << 1        /* covariance update (I-KH) P (I-KH)^T + K V K^T, in FP64 */
+};
+#define KF_F_PRECISION (KF_F_FP64_INVERSE | KF_F_JOSEPH)
+
+/* per-track status word: flag bits, plus the number of layers applied in
+ * bits 16..31 */
+enum {
+  KF_S_NONFINITE = 1,       /* a NaN or Inf entered or came out of the update */
+  KF_S_NOT_PD = 2,          /* S failed Sylvester's criterion */
+  KF_S_NO_CROSSING = 4,     /* the helix never reaches the cylinder */
+  KF_S_NEWTON_RESIDUAL = 8  /* the cylinder iteration ended off the surface */
+};
+#define KF_S_LAYERS_SHIFT 16
+
+/*
+ * kf_propagate_update_z -- filter n_tracks tracks through endcap planes
+ * z = layer_z[l] (Sec. 3.2, "propagation to z": the expected helical
+ * trajectory to layer N+1, then the Kalman update with that layer's hit).
+ *
+ *   par_in, cov_in    track parameters (6) and covariance (21) per track, in `layout`
+ *   par_out, cov_out  results, same layout; may equal par_in / cov_in
+ *   hit_pos, hit_cov  per layer and track: hit position (3) and covariance (6),
+ *                     in `layout` (per-layer form)
+ *   layer_z           HOST [n_layers], plane positions in cm
+ *   n_layers          0 .. KF_MAX_LAYERS
+ *   n_layers_per_track  [n_tracks] int32 or NULL: track i uses its first
+ *                     min(max(n,0), n_layers) layers (NULL: all n_layers)
+ *   n_tracks          >= 0 (0: nothing is enqueued)
+ *   bz_tesla          uniform solenoid field
+ *   flags             0 (FP32 throughout) or KF_F_* bits
+ *   chi2_out          [n_tracks] summed chi-square of the applied layers, or NULL
+ *   status_out        [n_tracks] status words, or NULL
+ *   ckpt_out          NULL, or [n_layers][27] per track in `layout` (per-layer
+ *                     form, E = 27): the state (6 parameters, then the 21
+ *                     covariance numbers) that entered layer l; layers a track
+ *                     does not reach are left untouched.  Used by kf_chi2_backward.
+ *   tune              NULL or a launch shape
+ *
+ * The plane is reached after the transverse path s = (z_l - z) tan(theta);
+ * the propagated z equals z_l exactly and the covariance's z row and column
+ * become zero (a plane fixes z).
+ */
+kf_status_t kf_propagate_update_z(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+    const float* hit_pos, const float* hit_cov, const float* layer_z, int32_t n_layers,
+    const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
+    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out,
+    const kf_tune_t* tune, void* stream);
+
+/*
+ * kf_propagate_update_r -- the same through barrel cylinders r = layer_r[l]
+ * (Sec. 3.2, "propagation to r": an iterative approach that advances the
+ * track state to the next radius).  The crossing is the first one at positive
+ * path length; it is found from a straight-line start by five Newton steps on
+ * x(s)^2 + y(s)^2 - r^2, after a closed-form test that the helix reaches the
+ * cylinder at all (KF_S_NO_CROSSING otherwise).  A crossing whose radius still
+ * misses r_l by more than 1e-4 * r_l after the five steps sets
+ * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z; ckpt_out is
+ * not supported here and must be NULL (KF_E_UNSUPPORTED).
+ */
+kf_status_t kf_propagate_update_r(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+    const float* hit_pos, const float* hit_cov, const float* layer_r, int32_t n_layers,
+    const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
+    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out,
+    const kf_tune_t* tune, void* stream);
+
+/* Copy between KF_SOA and another layout for an array of n_elem elements per
+ * track (n_layers_or_1 = 1 for per-track arrays, the layer count for
+ * per-layer arrays).  dst and src must not overlap. */
+kf_status_t kf_pack(const float* src_soa, float* dst, int32_t n_elem, int32_t n_layers_or_1,
+                    int64_t n_tracks, kf_layout_t layout, void* stream);
+kf_status_t kf_unpack(const float* src, float* dst_soa, int32_t n_elem, int32_t n_layers_or_1,
+                      int64_t n_tracks, kf_layout_t layout, void* stream);
+
+/* Number of floats an array of n_elem per track (and n_layers_or_1 layers)
+ * occupies in `layout`; 0 for an invalid layout. */
+int64_t kf_array_floats(int32_t n_elem, int32_t n_layers_or_1, int64_t n_tracks, kf_layout_t layout);
+
+const char* kf_status_string(kf_status_t status);
+int kf_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KF_H */

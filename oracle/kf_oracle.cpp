@@ -35,7 +35,9 @@
 //   positive definite, bit 2 cylinder not reachable, bit 3 reserved for the
 //   iterative propagation's residual check (never set here); bits 16..31 hold
 //   the number of layers applied.  A track stops at its first failing layer
-//   and keeps the state from before that layer.
+//   and keeps the state from before that layer.  Within a layer the checks
+//   run in this order: surface reachable; hit, propagated state and Jacobian
+//   finite; residual covariance positive definite; updated state finite.
 //   Process noise is zero (no material effects).
 
 #include <array>
@@ -341,12 +343,17 @@ void run_track(int geom, V6<S>& p, M6<S>& P, const V3<S>* hits, const M3<S>* hco
   chi2 = S(0.0);
   if (!finite_vec(p) || !finite_mat(P)) flags |= ST_NONFINITE;
   for (int k = 0; k < nl && !flags; ++k) {
-    if (!finite_vec(hits[k]) || !finite_mat(hcov[k])) { flags |= ST_NONFINITE; break; }
+    // order of the checks: the surface must be reachable; then every value
+    // entering the update must be finite; then S must be positive definite;
+    // then the updated state must be finite.
     M6<S> F;
     uint32_t f = 0;
     V6<S> pt = propagate(geom, p, layers[k], b, F, f);
     if (f) { flags |= f; break; }
-    if (!finite_vec(pt) || !finite_mat(F)) { flags |= ST_NONFINITE; break; }
+    if (!finite_vec(hits[k]) || !finite_mat(hcov[k]) || !finite_vec(pt) || !finite_mat(F)) {
+      flags |= ST_NONFINITE;
+      break;
+    }
     M6<S> Pt = matmul<S, 6, 6, 6>(matmul<S, 6, 6, 6>(F, P), transpose<S, 6, 6>(F));
     S dchi;
     if (!kalman_update(pt, Pt, hits[k], hcov[k], joseph, dchi, f)) { flags |= f; break; }

@@ -1,0 +1,56 @@
+"""Build libkf.so (HIP, gfx950) in-tree with hipcc.
+
+    python -m paper_2409_09228_amd.build            # build
+    python -m paper_2409_09228_amd.build --resource  # also print VGPR/SGPR/LDS use per kernel
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libkf.so")
+SOURCES = ["kf_api.hip", "kf_step.hip"]
+HEADERS = ["kf_device.h", "kf_internal.h", "kf_lanes.h"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ARCH = "gfx950"
+
+FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # never emit packed FP32 instructions (v_pk_fma_f32 and friends)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+    "-Wno-unused-command-line-argument",
+    "-Wno-bitwise-instead-of-logical",
+    f"-I{os.path.join(ROOT, 'include')}",
+]
+
+
+def build(resource_usage: bool = False, verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [HIPCC, *FLAGS, *srcs, "-o", LIB + ".tmp"]
+    if resource_usage:
+        cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building libkf.so")
+    if resource_usage or verbose:
+        sys.stderr.write(r.stderr)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(resource_usage="--resource" in sys.argv, verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,454 @@
+// Device-side building blocks of the Kalman-filter step for gfx950.
+//
+// One lane carries one track.  Its state -- 6 parameters and the 21 packed
+// covariance numbers -- lives in VGPRs for the whole layer loop; every index
+// below is a compile-time constant after unrolling, so no array is ever
+// spilled to scratch.  The 6x6 and 3x3 products are far too small for MFMA
+// tiles, so everything is per-lane VALU arithmetic, written against the
+// sparsity of the propagation Jacobian.
+//
+// Parameter order p = (x, y, z, kappa = q/pT, phi, theta); transverse
+// curvature omega = -b kappa with b = 0.00299792458 * Bz.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kf {
+
+enum : uint32_t { S_NONFINITE = 1u, S_NOT_PD = 2u, S_NO_CROSSING = 4u, S_NEWTON = 8u };
+
+// packed lower-triangle index of symmetric element (i, j)
+__host__ __device__ constexpr int ix(int i, int j) {
+  return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i;
+}
+
+// 1-ulp hardware reciprocal.  Every quantity inverted with it is well away
+// from zero and overflow in the domains checked by the callers, and its
+// error is far below the FP32 tolerance of the step.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ bool fin(float x) { return __builtin_isfinite(x); }
+__device__ __forceinline__ bool fin(double x) { return __builtin_isfinite(x); }
+
+// sin and cos of x.  For |x| <= 8192: x = k pi/2 + r with |r| <= pi/4 by
+// Cody-Waite reduction (pi/2 split into two floats, fused multiply-adds;
+// the split's residual 1.7e-15 times |k| <= 5216 stays below 1e-11), then the
+// Taylor polynomials of sin through r^9 and of cos through r^10 (truncation
+// below 3e-9 relative on |r| <= pi/4), and the quarter-turn rotation by k mod 4.
+// Larger or non-finite x go to the library sincosf.
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c) {
+  if (!(fabsf(x) <= 8192.0f)) {
+    sincosf(x, s, c);
+    return;
+  }
+  const float kf = __builtin_rintf(x * 0x1.45f306p-1f);  // x * 2/pi
+  float r = __builtin_fmaf(kf, -0x1.921fb6p+0f, x);       // - k * (pi/2 high part)
+  r = __builtin_fmaf(kf, 0x1.777a5cp-25f, r);             // - k * (pi/2 low part), low part < 0
+  const float r2 = r * r;
+  const float sp = __builtin_fmaf(
+      r * r2, -1.0f / 6.0f + r2 * (1.0f / 120.0f + r2 * (-1.0f / 5040.0f + r2 * (1.0f / 362880.0f))), r);
+  const float cp =
+      1.0f + r2 * (-0.5f + r2 * (1.0f / 24.0f + r2 * (-1.0f / 720.0f + r2 * (1.0f / 40320.0f + r2 * (-1.0f / 3628800.0f)))));
+  const int k = int(kf);
+  const bool swap = (k & 1) != 0;
+  const float sv = swap ? cp : sp;
+  const float cv = swap ? sp : cp;
+  *s = __int_as_float(__float_as_int(sv) ^ ((k & 2) << 30));
+  *c = __int_as_float(__float_as_int(cv) ^ (((k + 1) & 2) << 30));
+}
+
+// sinc(u) = sin(u)/u and G(u) = (sin u - u cos u)/u^2 = -d sinc/du.
+// |u| < 1/2: their Taylor series (relative truncation error < 1e-10, and no
+// cancellation); otherwise the closed forms.  su, cu = sin u, cos u.
+__device__ __forceinline__ void sinc_g(float u, float su, float cu, float& sinc, float& g) {
+  const float u2 = u * u;
+  const float ss = 1.0f - u2 * (1.0f / 6.0f) * (1.0f - u2 * (1.0f / 20.0f) * (1.0f - u2 * (1.0f / 42.0f) * (1.0f - u2 * (1.0f / 72.0f))));
+  const float gs = u * (1.0f / 3.0f - u2 * (1.0f / 30.0f - u2 * (1.0f / 840.0f - u2 * (1.0f / 45360.0f - u2 * (1.0f / 3991680.0f)))));
+  const float ru = rcp(u);
+  const bool small = fabsf(u) < 0.5f;
+  sinc = small ? ss : su * ru;
+  g = small ? gs : (su - u * cu) * ru * ru;
+}
+
+__device__ __forceinline__ float sinc_only(float u, float su) {
+  const float u2 = u * u;
+  const float ss = 1.0f - u2 * (1.0f / 6.0f) * (1.0f - u2 * (1.0f / 20.0f) * (1.0f - u2 * (1.0f / 42.0f) * (1.0f - u2 * (1.0f / 72.0f))));
+  return fabsf(u) < 0.5f ? ss : su * rcp(u);
+}
+
+// ----------------------------------------------------------------------------
+// Propagation to a plane z = zk.  Output: propagated parameters q and the
+// transported covariance Pt = F C F^T.
+//
+// The transverse path to the plane is s = (zk - z) tan(theta).  With
+// u = omega s / 2 and A = phi + u the helix moves by
+//   dx = s sinc(u) cos A,  dy = s sinc(u) sin A,  dphi = omega s
+// (the cancellation-free chord form), and z lands exactly on zk.
+// F = J_s + (dp/ds) (grad s)^T, with J_s the fixed-s partials:
+//   d dx/d omega = -(s^2/2)(sin A sinc u + cos A G(u)),
+//   d dy/d omega =  (s^2/2)(cos A sinc u - sin A G(u)),
+//   d dx/d phi = -dy, d dy/d phi = dx, d phi'/d kappa = -b s,
+// dp/ds = (cos phi', sin phi', cot theta, 0, omega, 0) and
+// grad s = (0, 0, -tan theta, 0, 0, (zk - z)/cos^2 theta).  The z row of F is
+// identically zero, so the z row and column of Pt vanish.
+__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], float zk, float b,
+                                            float q[6], float Pt[21]) {
+  float sth, cth, sp, cp;
+  sincos_r(p[5], &sth, &cth);
+  sincos_r(p[4], &sp, &cp);
+  const float rcth = rcp(cth);
+  const float tanth = sth * rcth;
+  const float dz = zk - p[2];
+  const float s = dz * tanth;
+  const float om = -b * p[3];
+  const float u = 0.5f * om * s;
+  float su, cu;
+  sincos_r(u, &su, &cu);
+  float sinc, g;
+  sinc_g(u, su, cu, sinc, g);
+  const float cA = cp * cu - sp * su;
+  const float sA = sp * cu + cp * su;
+  const float chord = s * sinc;
+  const float dx = chord * cA;
+  const float dy = chord * sA;
+  const float cP = cA * cu - sA * su;  // direction at the plane
+  const float sP = sA * cu + cA * su;
+  q[0] = p[0] + dx;
+  q[1] = p[1] + dy;
+  q[2] = zk;
+  q[3] = p[3];
+  q[4] = p[4] + om * s;
+  q[5] = p[5];
+
+  const float hs2 = 0.5f * s * s;
+  const float dxdom = -hs2 * (sA * sinc + cA * g);
+  const float dydom = hs2 * (cA * sinc - sA * g);
+  const float dsdth = dz * rcth * rcth;
+  // F row x = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th, likewise row y (b*),
+  // row phi = c0 e_z + c1 e_k + e_phi + c3 e_th; rows kappa, theta = identity.
+  const float a0 = -tanth * cP, a1 = -b * dxdom, a2 = -dy, a3 = cP * dsdth;
+  const float b0 = -tanth * sP, b1 = -b * dydom, b2 = dx, b3 = sP * dsdth;
+  const float c0 = -om * tanth, c1 = -b * s, c3 = om * dsdth;
+
+  // W_r = C F_r^T (column r of C F^T) for the three non-trivial rows
+  float Wx[6], Wy[6], Wf[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float c2 = C[ix(i, 2)], c3_ = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
+    Wx[i] = C[ix(i, 0)] + a0 * c2 + a1 * c3_ + a2 * c4 + a3 * c5;
+    Wy[i] = C[ix(i, 1)] + b0 * c2 + b1 * c3_ + b2 * c4 + b3 * c5;
+    Wf[i] = c0 * c2 + c1 * c3_ + c4 + c3 * c5;
+  }
+  Pt[ix(0, 0)] = Wx[0] + a0 * Wx[2] + a1 * Wx[3] + a2 * Wx[4] + a3 * Wx[5];
+  Pt[ix(1, 0)] = Wx[1] + b0 * Wx[2] + b1 * Wx[3] + b2 * Wx[4] + b3 * Wx[5];
+  Pt[ix(1, 1)] = Wy[1] + b0 * Wy[2] + b1 * Wy[3] + b2 * Wy[4] + b3 * Wy[5];
+  Pt[ix(2, 0)] = 0.0f;
+  Pt[ix(2, 1)] = 0.0f;
+  Pt[ix(2, 2)] = 0.0f;
+  Pt[ix(3, 0)] = Wx[3];
+  Pt[ix(3, 1)] = Wy[3];
+  Pt[ix(3, 2)] = 0.0f;
+  Pt[ix(3, 3)] = C[ix(3, 3)];
+  Pt[ix(4, 0)] = c0 * Wx[2] + c1 * Wx[3] + Wx[4] + c3 * Wx[5];
+  Pt[ix(4, 1)] = c0 * Wy[2] + c1 * Wy[3] + Wy[4] + c3 * Wy[5];
+  Pt[ix(4, 2)] = 0.0f;
+  Pt[ix(4, 3)] = c0 * C[ix(2, 3)] + c1 * C[ix(3, 3)] + C[ix(4, 3)] + c3 * C[ix(5, 3)];
+  Pt[ix(4, 4)] = c0 * Wf[2] + c1 * Wf[3] + Wf[4] + c3 * Wf[5];
+  Pt[ix(5, 0)] = Wx[5];
+  Pt[ix(5, 1)] = Wy[5];
+  Pt[ix(5, 2)] = 0.0f;
+  Pt[ix(5, 3)] = C[ix(5, 3)];
+  Pt[ix(5, 4)] = Wf[5];
+  Pt[ix(5, 5)] = C[ix(5, 5)];
+}
+
+// ----------------------------------------------------------------------------
+// Propagation to a cylinder r = rk: first crossing at s > 0.
+//
+// Reachability in closed form: with rho0^2 = x^2 + y^2 the helix meets the
+// cylinder iff |omega (rk^2 - rho0^2)/2 + x sin(phi) - y cos(phi)| <= rk
+// (for omega -> 0: the line's distance from the axis is at most rk).  The
+// crossing itself: straight-line start s0 = -beta + sqrt(beta^2 - rho0^2 + rk^2),
+// beta = x cos phi + y sin phi, then 5 Newton steps on
+// g(s) = x(s)^2 + y(s)^2 - rk^2, g'(s) = 2 (x(s) cos phi(s) + y(s) sin phi(s)).
+// The Jacobian adds to the fixed-s partials the path-length term with
+// grad s = -(x J_s[x,:] + y J_s[y,:]) / (x cos phi' + y sin phi'),
+// which keeps the propagated point on the cylinder to first order.
+// Branch-free; returns status bits (0 on success): an unreachable cylinder
+// first, then a crossing the iteration did not land on.
+__device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[21], float rk, float b,
+                                                float q[6], float Pt[21]) {
+  float sth, cth, sp, cp;
+  sincos_r(p[5], &sth, &cth);
+  sincos_r(p[4], &sp, &cp);
+  const float om = -b * p[3];
+  const float x = p[0], y = p[1];
+  const float rho2 = x * x + y * y;
+  const float rk2 = rk * rk;
+  const float reach = 0.5f * om * (rk2 - rho2) + (x * sp - y * cp);
+  const bool reachable = fabsf(reach) <= rk;
+  const float beta = x * cp + y * sp;
+  float s = -beta + sqrtf(fmaxf(beta * beta - rho2 + rk2, 0.0f));
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const float u = 0.5f * om * s;
+    float su, cu;
+    sincos_r(u, &su, &cu);
+    const float sinc = sinc_only(u, su);
+    const float cA = cp * cu - sp * su;
+    const float sA = sp * cu + cp * su;
+    const float ch = s * sinc;
+    const float X = x + ch * cA;
+    const float Y = y + ch * sA;
+    const float cP = cA * cu - sA * su;
+    const float sP = sA * cu + cA * su;
+    const float gg = X * X + Y * Y - rk2;
+    const float gp = 2.0f * (X * cP + Y * sP);
+    s = s - gg * rcp(gp);
+  }
+  const float u = 0.5f * om * s;
+  float su, cu;
+  sincos_r(u, &su, &cu);
+  float sinc, g;
+  sinc_g(u, su, cu, sinc, g);
+  const float cA = cp * cu - sp * su;
+  const float sA = sp * cu + cp * su;
+  const float ch = s * sinc;
+  const float dx = ch * cA, dy = ch * sA;
+  const float X = x + dx, Y = y + dy;
+  const float cP = cA * cu - sA * su;
+  const float sP = sA * cu + cA * su;
+  const bool on_surface = fabsf(X * X + Y * Y - rk2) <= 2.0e-4f * rk2;
+  const float rsth = rcp(sth);
+  const float cot = cth * rsth;
+  q[0] = X;
+  q[1] = Y;
+  q[2] = p[2] + s * cot;
+  q[3] = p[3];
+  q[4] = p[4] + om * s;
+  q[5] = p[5];
+
+  const float hs2 = 0.5f * s * s;
+  const float Jxk = b * hs2 * (sA * sinc + cA * g);   // -b d dx/d omega
+  const float Jyk = -b * hs2 * (cA * sinc - sA * g);  // -b d dy/d omega
+  const float Jxf = -dy, Jyf = dx;
+  const float Jzt = -s * rsth * rsth;
+  const float Jfk = -b * s;
+  const float rD = rcp(X * cP + Y * sP);
+  const float dsx = -X * rD, dsy = -Y * rD;
+  const float dsk = -(X * Jxk + Y * Jyk) * rD;
+  const float dsf = -(X * Jxf + Y * Jyf) * rD;
+  // F rows x, y, phi live in columns (x, y, kappa, phi); row z in all six.
+  const float Fx0 = 1.0f + cP * dsx, Fx1 = cP * dsy, Fx3 = Jxk + cP * dsk, Fx4 = Jxf + cP * dsf;
+  const float Fy0 = sP * dsx, Fy1 = 1.0f + sP * dsy, Fy3 = Jyk + sP * dsk, Fy4 = Jyf + sP * dsf;
+  const float Fz0 = cot * dsx, Fz1 = cot * dsy, Fz3 = cot * dsk, Fz4 = cot * dsf, Fz5 = Jzt;
+  const float Ff0 = om * dsx, Ff1 = om * dsy, Ff3 = Jfk + om * dsk, Ff4 = 1.0f + om * dsf;
+
+  float Wx[6], Wy[6], Wz[6], Wf[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const float c0 = C[ix(i, 0)], c1 = C[ix(i, 1)], c2 = C[ix(i, 2)], c3 = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
+    Wx[i] = Fx0 * c0 + Fx1 * c1 + Fx3 * c3 + Fx4 * c4;
+    Wy[i] = Fy0 * c0 + Fy1 * c1 + Fy3 * c3 + Fy4 * c4;
+    Wz[i] = Fz0 * c0 + Fz1 * c1 + c2 + Fz3 * c3 + Fz4 * c4 + Fz5 * c5;
+    Wf[i] = Ff0 * c0 + Ff1 * c1 + Ff3 * c3 + Ff4 * c4;
+  }
+  Pt[ix(0, 0)] = Fx0 * Wx[0] + Fx1 * Wx[1] + Fx3 * Wx[3] + Fx4 * Wx[4];
+  Pt[ix(1, 0)] = Fy0 * Wx[0] + Fy1 * Wx[1] + Fy3 * Wx[3] + Fy4 * Wx[4];
+  Pt[ix(1, 1)] = Fy0 * Wy[0] + Fy1 * Wy[1] + Fy3 * Wy[3] + Fy4 * Wy[4];
+  Pt[ix(2, 0)] = Fz0 * Wx[0] + Fz1 * Wx[1] + Wx[2] + Fz3 * Wx[3] + Fz4 * Wx[4] + Fz5 * Wx[5];
+  Pt[ix(2, 1)] = Fz0 * Wy[0] + Fz1 * Wy[1] + Wy[2] + Fz3 * Wy[3] + Fz4 * Wy[4] + Fz5 * Wy[5];
+  Pt[ix(2, 2)] = Fz0 * Wz[0] + Fz1 * Wz[1] + Wz[2] + Fz3 * Wz[3] + Fz4 * Wz[4] + Fz5 * Wz[5];
+  Pt[ix(3, 0)] = Wx[3];
+  Pt[ix(3, 1)] = Wy[3];
+  Pt[ix(3, 2)] = Wz[3];
+  Pt[ix(3, 3)] = C[ix(3, 3)];
+  Pt[ix(4, 0)] = Ff0 * Wx[0] + Ff1 * Wx[1] + Ff3 * Wx[3] + Ff4 * Wx[4];
+  Pt[ix(4, 1)] = Ff0 * Wy[0] + Ff1 * Wy[1] + Ff3 * Wy[3] + Ff4 * Wy[4];
+  Pt[ix(4, 2)] = Ff0 * Wz[0] + Ff1 * Wz[1] + Ff3 * Wz[3] + Ff4 * Wz[4];
+  Pt[ix(4, 3)] = Ff0 * C[ix(0, 3)] + Ff1 * C[ix(1, 3)] + Ff3 * C[ix(3, 3)] + Ff4 * C[ix(4, 3)];
+  Pt[ix(4, 4)] = Ff0 * Wf[0] + Ff1 * Wf[1] + Ff3 * Wf[3] + Ff4 * Wf[4];
+  Pt[ix(5, 0)] = Wx[5];
+  Pt[ix(5, 1)] = Wy[5];
+  Pt[ix(5, 2)] = Wz[5];
+  Pt[ix(5, 3)] = C[ix(5, 3)];
+  Pt[ix(5, 4)] = Wf[5];
+  Pt[ix(5, 5)] = C[ix(5, 5)];
+  return !reachable ? S_NO_CROSSING : (!on_surface ? S_NEWTON : 0u);
+}
+
+// ----------------------------------------------------------------------------
+// Kalman update with a 3D position hit m, covariance V (packed 6), H = [I3|0]:
+//   r = m - q_xyz, S = Pt_xyz + V, K = Pt_{:,xyz} S^-1,
+//   q' = q + K r, P' = Pt - K Pt_{xyz,:}, chi2 = r^T S^-1 r.
+// S^-1 from the symmetric cofactors over det S; S must pass Sylvester's
+// criterion (S00 > 0, leading 2x2 minor > 0, det > 0).
+// ZROW: the z row/column of Pt is known to be zero (planes), which removes
+// one column from every product.
+// Branch-free: every lane computes the whole update; q, Pt always receive the
+// updated values and the returned status bits (0 on success) say whether they
+// may be used.  The checks come in a fixed order: non-finite r or S, then S
+// not positive definite, then a non-finite result.
+template <bool ZROW>
+__device__ __forceinline__ uint32_t update_f32(float q[6], float Pt[21], const float m[3], const float V[6],
+                                               float& dchi) {
+  const float r0 = m[0] - q[0], r1 = m[1] - q[1], r2 = m[2] - q[2];
+  const float S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
+  const float S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
+  const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
+  const float c00 = S11 * S22 - S21 * S21;
+  const float c10 = S20 * S21 - S10 * S22;
+  const float c11 = S00 * S22 - S20 * S20;
+  const float c20 = S10 * S21 - S11 * S20;
+  const float c21 = S10 * S20 - S00 * S21;
+  const float c22 = S00 * S11 - S10 * S10;
+  const float det = S00 * c00 + S10 * c10 + S20 * c20;
+  const bool pd = (S00 > 0.0f) & (c22 > 0.0f) & (det > 0.0f);
+  const float rdet = rcp(det);
+  const float i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
+  const float i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
+  // t = S^-1 r
+  const float t0 = i00 * r0 + i10 * r1 + i20 * r2;
+  const float t1 = i10 * r0 + i11 * r1 + i21 * r2;
+  const float t2 = i20 * r0 + i21 * r1 + i22 * r2;
+  dchi = r0 * t0 + r1 * t1 + r2 * t2;
+  if (ZROW) {
+    // row/column 2 of Pt vanish: K_i = Pt_i0 S^-1_0: + Pt_i1 S^-1_1:
+    float K0[6], K1[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      if (i == 2) continue;
+      const float a = Pt[ix(i, 0)], c = Pt[ix(i, 1)];
+      K0[i] = a * i00 + c * i10;
+      K1[i] = a * i10 + c * i11;
+    }
+    float Pn[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j)
+        Pn[ix(i, j)] = (i == 2 || j == 2) ? 0.0f : Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (i != 2) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1;
+#pragma unroll
+    for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
+  } else {
+    float K0[6], K1[6], K2[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const float a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
+      K0[i] = a * i00 + c * i10 + d * i20;
+      K1[i] = a * i10 + c * i11 + d * i21;
+      K2[i] = a * i20 + c * i21 + d * i22;
+    }
+    float Pn[21];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j)
+        Pn[ix(i, j)] = Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)] - K2[i] * Pt[ix(2, j)];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1 + Pt[ix(i, 2)] * t2;
+#pragma unroll
+    for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
+  }
+  bool out_ok = fin(dchi);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out_ok = out_ok & fin(q[i]) & fin(Pt[ix(i, i)]);
+  return !in_ok ? S_NONFINITE : (!pd ? S_NOT_PD : (!out_ok ? S_NONFINITE : 0u));
+}
+
+// The precision form: S, S^-1, the gain and the state update in FP64; the
+// covariance update in FP64 too, in plain form or, with JOSEPH, as
+//   P' = (I - K H) Pt (I - K H)^T + K V K^T
+// (symmetric and positive semi-definite by construction).  Bulk state stays FP32.
+template <bool JOSEPH>
+__device__ __forceinline__ uint32_t update_f64(float q[6], float Pt[21], const float m[3], const float V[6],
+                                               float& dchi) {
+  const double r0 = (double)m[0] - (double)q[0], r1 = (double)m[1] - (double)q[1], r2 = (double)m[2] - (double)q[2];
+  const double S00 = (double)Pt[0] + V[0], S10 = (double)Pt[1] + V[1], S11 = (double)Pt[2] + V[2];
+  const double S20 = (double)Pt[3] + V[3], S21 = (double)Pt[4] + V[4], S22 = (double)Pt[5] + V[5];
+  const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
+  const double c00 = S11 * S22 - S21 * S21;
+  const double c10 = S20 * S21 - S10 * S22;
+  const double c11 = S00 * S22 - S20 * S20;
+  const double c20 = S10 * S21 - S11 * S20;
+  const double c21 = S10 * S20 - S00 * S21;
+  const double c22 = S00 * S11 - S10 * S10;
+  const double det = S00 * c00 + S10 * c10 + S20 * c20;
+  const bool pd = (S00 > 0.0) & (c22 > 0.0) & (det > 0.0);
+  const double rdet = 1.0 / det;
+  const double i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
+  const double i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
+  const double t0 = i00 * r0 + i10 * r1 + i20 * r2;
+  const double t1 = i10 * r0 + i11 * r1 + i21 * r2;
+  const double t2 = i20 * r0 + i21 * r1 + i22 * r2;
+  const double chi = r0 * t0 + r1 * t1 + r2 * t2;
+  double K0[6], K1[6], K2[6];
+  float qn[6], Pn[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const double a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
+    K0[i] = a * i00 + c * i10 + d * i20;
+    K1[i] = a * i10 + c * i11 + d * i21;
+    K2[i] = a * i20 + c * i21 + d * i22;
+    qn[i] = (float)((double)q[i] + a * t0 + c * t1 + d * t2);
+  }
+  if (!JOSEPH) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j)
+        Pn[ix(i, j)] = (float)((double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] -
+                               K1[i] * (double)Pt[ix(1, j)] - K2[i] * (double)Pt[ix(2, j)]);
+  } else {
+    const double v00 = V[0], v10 = V[1], v11 = V[2], v20 = V[3], v21 = V[4], v22 = V[5];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      // row i of M = Pt - K Pt_{xyz,:}, then (M - K V)_{i,0:3}
+      double M[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        M[j] = (double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] - K1[i] * (double)Pt[ix(1, j)] -
+               K2[i] * (double)Pt[ix(2, j)];
+      const double e0 = M[0] - (K0[i] * v00 + K1[i] * v10 + K2[i] * v20);
+      const double e1 = M[1] - (K0[i] * v10 + K1[i] * v11 + K2[i] * v21);
+      const double e2 = M[2] - (K0[i] * v20 + K1[i] * v21 + K2[i] * v22);
+#pragma unroll
+      for (int j = 0; j <= i; ++j) Pn[ix(i, j)] = (float)(M[j] - e0 * K0[j] - e1 * K1[j] - e2 * K2[j]);
+    }
+  }
+  dchi = (float)chi;
+  bool out_ok = fin(dchi);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) out_ok = out_ok & fin(qn[i]) & fin(Pn[ix(i, i)]);
+#pragma unroll
+  for (int i = 0; i < 6; ++i) q[i] = qn[i];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
+  return !in_ok ? S_NONFINITE : (!pd ? S_NOT_PD : (!out_ok ? S_NONFINITE : 0u));
+}
+
+// precision variants of the update
+enum { PREC_F32 = 0, PREC_F64 = 1, PREC_F64_JOSEPH = 2 };
+
+template <int GEOM, int PREC>
+__device__ __forceinline__ uint32_t update(float q[6], float Pt[21], const float m[3], const float V[6], float& dchi) {
+  if (PREC == PREC_F32) return update_f32<GEOM == 0>(q, Pt, m, V, dchi);
+  if (PREC == PREC_F64) return update_f64<false>(q, Pt, m, V, dchi);
+  return update_f64<true>(q, Pt, m, V, dchi);
+}
+
+template <int GEOM>
+__device__ __forceinline__ uint32_t propagate(const float p[6], const float C[21], float target, float b,
+                                              float q[6], float Pt[21]) {
+  if (GEOM == 0) {
+    propagate_z(p, C, target, b, q, Pt);
+    return 0u;
+  }
+  return propagate_r(p, C, target, b, q, Pt);
+}
+
+}  // namespace kf

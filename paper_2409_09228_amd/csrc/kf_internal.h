@@ -1,0 +1,44 @@
+// Internal host-side interface between the C ABI (kf_api.hip) and the kernel
+// launchers.  Not installed; the public interface is include/kf.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kf.h"
+
+namespace kf {
+
+// Where track i's element e (of E per track, layer l of L) sits:
+//   base(E, L) + (l * E + e) * es
+// SoA: blk = 0, lane = i, es = n.  AoSoA-B: blk = i / B, lane = i % B, es = B.
+struct TrackLayout {
+  int32_t aos;   // 0 SoA, 1 AoSoA
+  int32_t shift; // log2(B) for AoSoA
+};
+
+struct StepArgs {
+  const float* par_in;
+  const float* cov_in;
+  float* par_out;
+  float* cov_out;
+  const float* hit_pos;
+  const float* hit_cov;
+  const int32_t* nlay;
+  float* chi2;
+  int32_t* status;
+  float* ckpt;
+  int64_t n;
+  int32_t L;
+  TrackLayout lay;
+  float b;  // 0.00299792458 * Bz
+  float layer[KF_MAX_LAYERS];
+};
+
+// precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
+hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);
+
+hipError_t launch_pack(const float* src, float* dst, int32_t E, int32_t L, int64_t n, TrackLayout lay,
+                       bool to_layout, hipStream_t s);
+
+}  // namespace kf

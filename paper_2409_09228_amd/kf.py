@@ -1,0 +1,295 @@
+"""Python binding of libkf.so: argument marshalling only.
+
+Every step of the filter runs in the HIP kernels behind the C ABI declared in
+include/kf.h; this module turns torch CUDA tensors (device memory) and the
+current torch stream into the pointers the ABI takes.  There is no CPU
+fallback: if the library is missing or cannot run, calls raise.
+
+Tensor shapes (float32, on the GPU):
+  SoA layout:   par [6, n], cov [21, n], hit_pos [L, 3, n], hit_cov [L, 6, n]
+  AoSoA-B:      par [nb, 6, B], cov [nb, 21, B], hit_pos [nb, L, 3, B], ...
+                with nb = ceil(n / B)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkf.so")
+
+KF_OK = 0
+KF_SOA = 0
+KF_AOSOA = 1
+KF_F_FP64_INVERSE = 1
+KF_F_JOSEPH = 2
+KF_F_PRECISION = 3
+KF_MAX_LAYERS = 64
+S_NONFINITE = 1
+S_NOT_PD = 2
+S_NO_CROSSING = 4
+S_NEWTON_RESIDUAL = 8
+LAYERS_SHIFT = 16
+
+
+class KFError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {status_string(code)} (code {code})")
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("block", ctypes.c_int32)]
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("tracks_per_thread", ctypes.c_int32)]
+
+
+SOA = (KF_SOA, 0)
+
+
+def aosoa(block: int):
+    return (KF_AOSOA, int(block))
+
+
+_lib = None
+
+
+def lib():
+    """Load libkf.so (built by paper_2409_09228_amd.build); raise if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2409_09228_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, f32, i32, i64 = ctypes.c_void_p, ctypes.c_float, ctypes.c_int32, ctypes.c_int64
+        step_args = [vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, f32, Layout, ctypes.c_uint32, vp, vp, vp,
+                     ctypes.POINTER(Tune), vp]
+        for name in ("kf_propagate_update_z", "kf_propagate_update_r"):
+            fn = getattr(L, name)
+            fn.argtypes = step_args
+            fn.restype = ctypes.c_int
+        for name in ("kf_pack", "kf_unpack"):
+            fn = getattr(L, name)
+            fn.argtypes = [vp, vp, i32, i32, i64, Layout, vp]
+            fn.restype = ctypes.c_int
+        L.kf_array_floats.argtypes = [i32, i32, i64, Layout]
+        L.kf_array_floats.restype = ctypes.c_int64
+        L.kf_status_string.argtypes = [ctypes.c_int]
+        L.kf_status_string.restype = ctypes.c_char_p
+        L.kf_abi_version.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().kf_status_string(int(code)).decode()
+    except Exception:  # pragma: no cover
+        return "unknown"
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, where: str):
+    if rc != KF_OK:
+        raise KFError(rc, where)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("libkf works on GPU tensors only")
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+
+
+def array_floats(n_elem: int, n_layers: int, n: int, layout) -> int:
+    return int(lib().kf_array_floats(n_elem, n_layers, n, Layout(*layout)))
+
+
+def empty_like_layout(n_elem: int, n_layers: int, n: int, layout, device="cuda"):
+    """An uninitialised float32 tensor holding one array in `layout`."""
+    import torch
+    kind, B = layout
+    if kind == KF_SOA:
+        shape = (n_elem, n) if n_layers == 1 else (n_layers, n_elem, n)
+    else:
+        nb = (n + B - 1) // B
+        shape = (nb, n_elem, B) if n_layers == 1 else (nb, n_layers, n_elem, B)
+    return torch.empty(shape, dtype=torch.float32, device=device)
+
+
+def propagate_update(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n_tracks: int,
+                     nlay=None, layout=SOA, flags: int = 0, out=None, chi2=True, status=True,
+                     ckpt=None, tune=None, stream=None):
+    """One call of kf_propagate_update_z (geom 0) or _r (geom 1).
+
+    Returns (par_out, cov_out, chi2, status).  `out` = (par_out, cov_out) lets
+    the caller pass output buffers (possibly the inputs themselves).
+    """
+    import torch
+    layers = np.ascontiguousarray(layers, np.float32)
+    L = int(layers.shape[0])
+    _require_cuda(par, cov, hit_pos, hit_cov, nlay, ckpt)
+    if out is None:
+        par_out = torch.empty_like(par)
+        cov_out = torch.empty_like(cov)
+    else:
+        par_out, cov_out = out
+    dev = par.device
+    c2 = torch.empty(n_tracks, dtype=torch.float32, device=dev) if chi2 is True else chi2
+    st = torch.empty(n_tracks, dtype=torch.int32, device=dev) if status is True else status
+    if c2 is False:
+        c2 = None
+    if st is False:
+        st = None
+    tn = None if tune is None else ctypes.byref(Tune(int(tune[0]), int(tune[1])))
+    fn = lib().kf_propagate_update_z if geom == 0 else lib().kf_propagate_update_r
+    with torch.cuda.device(dev):
+        rc = fn(_ptr(par), _ptr(cov), _ptr(par_out), _ptr(cov_out), _ptr(hit_pos), _ptr(hit_cov),
+                layers.ctypes.data_as(ctypes.c_void_p), L, _ptr(nlay), int(n_tracks), float(bz),
+                Layout(*layout), int(flags), _ptr(c2), _ptr(st), _ptr(ckpt), tn, _stream(stream))
+    _check(rc, "kf_propagate_update_z" if geom == 0 else "kf_propagate_update_r")
+    return par_out, cov_out, c2, st
+
+
+class StepLauncher:
+    """A kf_propagate_update_z/_r call with every argument converted once.
+
+    Calling the object enqueues the step again on the same stream with the
+    same buffers -- the per-call host cost is one ctypes call, which keeps
+    back-to-back launches from starving the GPU.
+    """
+
+    def __init__(self, geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n_tracks: int,
+                 out, chi2, status, nlay=None, layout=SOA, flags: int = 0, ckpt=None, tune=None, stream=None):
+        import torch
+        _require_cuda(par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, *out)
+        self._layers = np.ascontiguousarray(layers, np.float32)
+        self._keep = (par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, out)
+        self._tune = None if tune is None else Tune(int(tune[0]), int(tune[1]))
+        self._fn = lib().kf_propagate_update_z if geom == 0 else lib().kf_propagate_update_r
+        self._name = "kf_propagate_update_z" if geom == 0 else "kf_propagate_update_r"
+        self._device = par.device
+        with torch.cuda.device(par.device):
+            st = _stream(stream)
+        self._args = (_ptr(par), _ptr(cov), _ptr(out[0]), _ptr(out[1]), _ptr(hit_pos), _ptr(hit_cov),
+                      self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]), _ptr(nlay),
+                      int(n_tracks), float(bz), Layout(*layout), int(flags), _ptr(chi2), _ptr(status),
+                      _ptr(ckpt), None if self._tune is None else ctypes.byref(self._tune), st)
+
+    def __call__(self):
+        rc = self._fn(*self._args)
+        if rc != KF_OK:
+            raise KFError(rc, self._name)
+
+
+def propagate_update_z(*args, **kw):
+    return propagate_update(0, *args, **kw)
+
+
+def propagate_update_r(*args, **kw):
+    return propagate_update(1, *args, **kw)
+
+
+def pack(src_soa, n_elem: int, n_layers: int, n: int, layout, dst=None, stream=None):
+    """SoA tensor -> `layout` (kf_pack)."""
+    import torch
+    _require_cuda(src_soa)
+    if dst is None:
+        dst = empty_like_layout(n_elem, n_layers, n, layout, src_soa.device)
+        if layout[0] != KF_SOA:
+            dst.zero_()
+    with torch.cuda.device(src_soa.device):
+        rc = lib().kf_pack(_ptr(src_soa), _ptr(dst), n_elem, n_layers, int(n), Layout(*layout), _stream(stream))
+    _check(rc, "kf_pack")
+    return dst
+
+
+def unpack(src, n_elem: int, n_layers: int, n: int, layout, dst=None, stream=None):
+    """`layout` tensor -> SoA (kf_unpack)."""
+    import torch
+    _require_cuda(src)
+    if dst is None:
+        dst = empty_like_layout(n_elem, n_layers, n, SOA, src.device)
+    with torch.cuda.device(src.device):
+        rc = lib().kf_unpack(_ptr(src), _ptr(dst), n_elem, n_layers, int(n), Layout(*layout), _stream(stream))
+    _check(rc, "kf_unpack")
+    return dst
+
+
+# ----------------------------------------------------------------------------
+# staging of logical host arrays (input preparation, outside the timed path)
+def to_soa_tensor(arr: np.ndarray, device="cuda"):
+    """Logical [n, E] -> SoA [E, n]; logical [L, n, E] -> [L, E, n] (float32)."""
+    import torch
+    a = np.asarray(arr, np.float32)
+    if a.ndim == 2:
+        a = a.T
+    else:
+        a = a.transpose(0, 2, 1)
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+
+def from_soa_tensor(t) -> np.ndarray:
+    """Inverse of to_soa_tensor, as a numpy array."""
+    a = t.detach().cpu().numpy()
+    return np.ascontiguousarray(a.T if a.ndim == 2 else a.transpose(0, 2, 1))
+
+
+def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
+    """Upload a synthetic sample (single geometry) as float32 device tensors in `layout`."""
+    import torch
+    n = sample["par"].shape[0]
+    L = sample["hit_pos"].shape[0]
+    soa = {
+        "par": to_soa_tensor(sample["par"], device),
+        "cov": to_soa_tensor(sample["cov"], device),
+        "hit_pos": to_soa_tensor(sample["hit_pos"], device),
+        "hit_cov": to_soa_tensor(sample["hit_cov"], device),
+    }
+    out = {"n": n, "L": L, "layout": layout, "bz": float(sample["bz"]),
+           "nlay": torch.from_numpy(np.ascontiguousarray(sample["nlay"], np.int32)).to(device)}
+    geom = int(sample["geom"][0]) if n else 0
+    out["geom"] = geom
+    out["layers"] = np.asarray(sample["layer_z"] if geom == 0 else sample["layer_r"], np.float32)[:L]
+    if layout[0] == KF_SOA:
+        out.update(soa)
+    else:
+        out["par"] = pack(soa["par"], 6, 1, n, layout)
+        out["cov"] = pack(soa["cov"], 21, 1, n, layout)
+        out["hit_pos"] = pack(soa["hit_pos"], 3, L, n, layout)
+        out["hit_cov"] = pack(soa["hit_cov"], 6, L, n, layout)
+    return out
+
+
+def run_staged(st: dict, flags: int = 0, out=None, ckpt=None, tune=None, stream=None, nlay=True):
+    """Filter a staged sample; returns (par_out, cov_out, chi2, status) tensors in its layout."""
+    return propagate_update(st["geom"], st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                            st["bz"], st["n"], nlay=st["nlay"] if nlay else None, layout=st["layout"],
+                            flags=flags, out=out, ckpt=ckpt, tune=tune, stream=stream)
+
+
+def results_to_logical(st: dict, par_out, cov_out):
+    """Device results in the staged layout -> logical numpy [n, 6], [n, 21] (float64)."""
+    n = st["n"]
+    lay = st["layout"]
+    if lay[0] != KF_SOA:
+        par_out = unpack(par_out, 6, 1, n, lay)
+        cov_out = unpack(cov_out, 21, 1, n, lay)
+    return from_soa_tensor(par_out).astype(np.float64), from_soa_tensor(cov_out).astype(np.float64)

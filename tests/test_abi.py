@@ -1,0 +1,74 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/kf.h declares, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_09228_amd import kf as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "kf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(kf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_function():
+    names = header_functions()
+    assert "kf_propagate_update_z" in names and "kf_propagate_update_r" in names
+    lib = ctypes.CDLL(K.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), f"libkf.so does not export {n}"
+
+
+def test_version_and_strings():
+    assert K.lib().kf_abi_version() == 1
+    assert K.status_string(0) == "ok"
+    assert "layout" in K.status_string(3)
+
+
+def test_array_floats():
+    assert K.array_floats(6, 1, 100, K.SOA) == 600
+    assert K.array_floats(6, 1, 100, K.aosoa(64)) == 6 * 128
+    assert K.array_floats(3, 20, 65, K.aosoa(16)) == 3 * 20 * 80
+    assert K.array_floats(6, 1, 100, (1, 48)) == 0
+
+
+def _call(fn_name, n=10, L=3, layout=K.SOA, flags=0, par=1024, tune=None, ckpt=None):
+    lib = K.lib()
+    fn = getattr(lib, fn_name)
+    layers = (ctypes.c_float * 4)(10, 15, 20, 25)
+    p = ctypes.c_void_p(par) if par else None
+    h = ctypes.c_void_p(4096)
+    tn = None if tune is None else ctypes.byref(K.Tune(*tune))
+    return fn(p, h, h, h, h, h, ctypes.cast(layers, ctypes.c_void_p), L, None, n, 3.8,
+              K.Layout(*layout), flags, None, None, ckpt, tn, None)
+
+
+@pytest.mark.parametrize("fn", ["kf_propagate_update_z", "kf_propagate_update_r"])
+def test_argument_validation_before_any_device_call(fn):
+    assert _call(fn, n=-1) == 2          # KF_E_SHAPE
+    assert _call(fn, L=65) == 2
+    assert _call(fn, L=-1) == 2
+    assert _call(fn, layout=(1, 48)) == 3  # KF_E_LAYOUT
+    assert _call(fn, layout=(7, 0)) == 3
+    assert _call(fn, flags=4) == 8       # KF_E_FLAGS
+    assert _call(fn, tune=(96, 1)) == 8
+    assert _call(fn, tune=(64, 3)) == 8
+    assert _call(fn, par=0) == 1         # KF_E_NULL
+    assert _call(fn, par=1026) == 4      # KF_E_ALIGN
+    assert _call(fn, n=0) == 0           # nothing to do
+    if fn.endswith("_r"):
+        assert _call(fn, ckpt=ctypes.c_void_p(8192)) == 9  # KF_E_UNSUPPORTED
+
+
+def test_pack_validation():
+    lib = K.lib()
+    assert lib.kf_pack(None, None, 0, 1, 10, K.Layout(1, 16), None) == 2
+    assert lib.kf_pack(None, None, 6, 1, 10, K.Layout(1, 12), None) == 3
+    assert lib.kf_pack(None, None, 6, 1, 10, K.Layout(1, 16), None) == 1
+    assert lib.kf_pack(None, None, 6, 1, 0, K.Layout(1, 16), None) == 0

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP kernels behind the C ABI against the FP64 oracle, on
+the same seeded inputs (tolerances and metrics in tests/parity.py)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_09228_amd import synth as S
+from parity import TOL_F32, TOL_PRECISION, assert_within, calibrated, metrics
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def kf():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2409_09228_amd import kf as K
+    K.lib()  # raises if libkf.so is missing
+    return K
+
+
+def _gpu_run(K, sample, layout=None, flags=0, tune=None):
+    layout = K.SOA if layout is None else layout
+    st = K.stage_sample(sample, layout)
+    po, co, c2, ss = K.run_staged(st, flags=flags, tune=tune)
+    torch.cuda.synchronize()
+    p, c = K.results_to_logical(st, po, co)
+    return p, c, c2.cpu().numpy().astype(np.float64), ss.cpu().numpy()
+
+
+def _oracle(sample, joseph=False):
+    return O.run_sample(sample, joseph=joseph)
+
+
+@pytest.mark.parametrize("layout", [None, ("aos", 16), ("aos", 32), ("aos", 64), ("aos", 128), ("aos", 256)])
+def test_p2z_8192_all_layouts(kf, layout):
+    s = S.generate("p2z_1x8192")
+    lay = None if layout is None else kf.aosoa(layout[1])
+    got = _gpu_run(kf, s, lay)
+    m = metrics(_oracle(s), got, 0)
+    print(layout, m)
+    assert_within(m, TOL_F32, f"p2z layout {layout}")
+    assert np.all(got[3] == 20 << 16)
+
+
+def test_p2r_9600(kf):
+    s = S.generate("p2r_100x9600", n_events=1)
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    m = metrics(ref, got, 1)
+    print(m)
+    assert_within(m, TOL_F32, "p2r")
+    np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
+
+
+@pytest.mark.parametrize("flags", [1, 3])
+@pytest.mark.parametrize("name", ["p2z_1x8192", "p2r_100x9600"])
+def test_precision_forms(kf, name, flags):
+    s = S.generate(name, n_events=1)
+    g = int(s["geom"][0])
+    got = _gpu_run(kf, s, flags=flags)
+    m = metrics(_oracle(s, joseph=bool(flags & 2)), got, g)
+    print(name, flags, m)
+    assert_within(m, TOL_PRECISION, f"{name} flags={flags}")
+
+
+@pytest.mark.parametrize("name,geom", [("p2z_100x9600", 0), ("p2r_100x9600", 1)])
+def test_full_size_sampled(kf, name, geom):
+    """The full 960k-track sample in the benchmark's launch shape; the oracle
+    recomputes 3000 sampled tracks one by one, and the sample means of all
+    outputs (the paper's own consistency check) must agree to 1e-5."""
+    s = S.generate(name)
+    n = s["par"].shape[0]
+    got = _gpu_run(kf, s)
+    rng = np.random.default_rng(123)
+    idx = np.sort(rng.choice(n, 3000, replace=False))
+    idx[-1] = n - 1
+    sub = S.subset(s, idx)
+    ref = _oracle(sub)
+    gsub = tuple(x[idx] for x in got)
+    m = metrics(ref, gsub, geom)
+    print(name, m)
+    assert_within(m, TOL_F32, name)
+    assert np.all((got[3] & 0xFF) == 0)
+    np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
+    # sample means over all tracks vs the oracle's means over the same sample:
+    # run the oracle on everything (FP64, a few seconds with all cores)
+    full = _oracle(s)
+    for k, (a, b) in enumerate(((full[0], got[0]), (full[2], got[2]))):
+        ma, mb = a.mean(0), b.mean(0)
+        assert np.all(np.abs(ma - mb) <= 1e-5 * np.maximum(np.abs(ma), 1.0)), (k, ma, mb)
+
+
+def test_in_place_equals_out_of_place(kf):
+    s = S.generate("p2z_1x8192")
+    st = kf.stage_sample(s)
+    po, co, c2, ss = kf.run_staged(st)
+    par, cov = st["par"].clone(), st["cov"].clone()
+    st2 = dict(st, par=par, cov=cov)
+    kf.run_staged(st2, out=(par, cov))
+    torch.cuda.synchronize()
+    assert torch.equal(par, po) and torch.equal(cov, co)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 1000])
+@pytest.mark.parametrize("B", [16, 64])
+def test_ragged_tails_match_soa(kf, n, B):
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(n))
+    a = _gpu_run(kf, s)
+    b = _gpu_run(kf, s, kf.aosoa(B))
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_empty_input_is_a_no_op(kf):
+    e = torch.empty(0, device="cuda")
+    out = kf.propagate_update_z(e, e, e, e, [10.0], 3.8, 0, out=(e, e), chi2=False, status=False)
+    assert out[0].numel() == 0
+
+
+def test_edge_statuses_match_oracle(kf):
+    """NaN hit, non-positive-definite S, non-finite input, zero and
+    over-long per-track layer counts -- identical status words and outputs
+    frozen at the same layer as the oracle."""
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(128))
+    s["hit_pos"] = s["hit_pos"].copy()
+    s["hit_cov"] = s["hit_cov"].copy()
+    s["par"] = s["par"].copy()
+    s["nlay"] = s["nlay"].copy()
+    s["hit_pos"][5, 2, 1] = np.nan
+    s["hit_cov"][9, 4] = O.pack_sym(-np.eye(3))
+    s["hit_cov"][0, 5] = np.inf
+    s["par"][6, 3] = np.inf
+    s["nlay"][7] = 0
+    s["nlay"][8] = 1000
+    s["nlay"][9] = -3
+    s["nlay"][10] = 7
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    ok = (ref[3] & 0xFF) == 0
+    m = metrics(ref, got, 0)
+    assert m["status_mismatch"] == 0
+    for i in (2, 4, 5, 6, 7, 9):
+        # frozen tracks: compare the frozen state (finite parts)
+        np.testing.assert_allclose(got[0][i][np.isfinite(ref[0][i])], ref[0][i][np.isfinite(ref[0][i])],
+                                   rtol=1e-4, atol=1e-4)
+    assert_within(metrics(ref, got, 0, mask=ok & np.all(np.isfinite(ref[0]), 1)), TOL_F32, "edge")
+
+
+def test_p2r_no_crossing_matches_oracle(kf):
+    r = S.generate("p2r_100x9600", n_events=1)
+    idx = np.nonzero(r["nlay"] < 10)[0][:200]
+    s = S.subset(r, idx)
+    s["par"] = s["truth"].copy()
+    pts = np.stack([S.truth_cross_cylinder(s["truth"], rk, r["bz"]) for rk in r["layer_r"]])
+    s["hit_pos"] = np.where(np.isfinite(pts), pts, 0.0)
+    s["nlay"] = np.full(len(idx), 20, np.int32)
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    assert np.all((ref[3] & 0xFF) == O.ST_NO_CROSSING)
+
+
+def test_max_layers(kf):
+    """64 planes (the longest layer table), z_k = 10 + 5k."""
+    w = S.Workload("p2z_64", "z", 1, 512, 64, seed_index=9)
+    s = S.generate(w)
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    m = metrics(ref, got, 0)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), 0)
+    print(m, f32)
+    assert_within(m, calibrated(TOL_F32, f32), "64 layers")
+
+
+def test_zero_layers(kf):
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(100))
+    st = kf.stage_sample(s)
+    po, co, c2, ss = kf.propagate_update_z(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], [], 3.8, 100)
+    torch.cuda.synchronize()
+    assert torch.equal(po, st["par"]) and torch.equal(co, st["cov"])
+    assert torch.all(c2 == 0) and torch.all(ss == 0)
+
+
+def test_pack_unpack_roundtrip(kf):
+    n, L = 1000, 5
+    x = torch.randn(L, 7, n, device="cuda")
+    for B in (16, 32, 64, 128, 256):
+        y = kf.pack(x, 7, L, n, kf.aosoa(B))
+        z = kf.unpack(y, 7, L, n, kf.aosoa(B))
+        assert torch.equal(x, z)
+        # spot-check the documented offset formula
+        yf = y.flatten()
+        i, l, e = 777, 3, 5
+        assert yf[((i // B) * L + l) * (7 * B) + e * B + i % B] == x[l, e, i]
+
+
+def test_bad_arguments_raise(kf):
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(10))
+    st = kf.stage_sample(s)
+    with pytest.raises(kf.KFError):
+        kf.run_staged(dict(st, layout=(1, 48)))
+    with pytest.raises(kf.KFError):
+        kf.run_staged(st, flags=8)
+    with pytest.raises(kf.KFError):
+        kf.run_staged(st, tune=(96, 1))
