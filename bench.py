@@ -41,6 +41,8 @@ def parse_layout(s: str):
     from paper_2409_09228_amd import kf as K
     if s == "soa":
         return K.SOA
+    if s == "aos":
+        return K.AOS
     if s.startswith("aosoa"):
         return K.aosoa(int(s[5:]))
     raise SystemExit(f"unknown layout {s}")
@@ -62,6 +64,84 @@ def cpu_baseline(sample, n_tracks: int):
                       f"FP64, OpenMP over tracks, {dt:.2f} s wall"}
 
 
+def time_launches(fn, steps: int, stream):
+    """Mean per-call GPU time (ms) of `fn` over `steps` calls after >= 300 ms of warm-up."""
+    import torch
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < 0.3:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_batched(args, sample):
+    """Mixed geometry, uneven layer counts: the persistent graph-replayed
+    launch against one plain launch per (geometry, layer count) bucket."""
+    import torch
+    from paper_2409_09228_amd import kf as K
+    from paper_2409_09228_amd import synth as S
+    stream = torch.cuda.current_stream()
+    layout = parse_layout(args.layout) if args.layout != "soa" else K.AOS
+    st = K.stage_batched(sample, layout)
+    n = st["n"]
+    updates = int(sample["nlay"].sum())
+    par_out, cov_out = torch.empty_like(st["par"]), torch.empty_like(st["cov"])
+    chi2 = torch.empty(n, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    launch = K.BatchedLauncher(st, (par_out, cov_out), chi2, status, flags=args.flags,
+                               tune=(args.block, args.tpt, args.sched, args.waves_mult), stream=stream)
+    ms = time_launches(launch, args.steps, stream)
+    ok = int(((status & 0xFF) == 0).sum().item())
+    # baseline: one launch of the plain kernel per (geometry, layer count) bucket
+    launches = []
+    if args.no_baseline:
+        ms_b = float("nan")
+    for g in ((0, 1) if not args.no_baseline else ()):
+        for nl in range(int(sample["nlay"].max()) + 1):
+            idx = np.nonzero((sample["geom"] == g) & (sample["nlay"] == nl))[0]
+            if len(idx) == 0 or nl == 0:
+                continue
+            sub = S.subset(sample, idx)
+            sub["hit_pos"] = sub["hit_pos"][:nl]
+            sub["hit_cov"] = sub["hit_cov"][:nl]
+            sb = K.stage_sample(sub, K.SOA)
+            outs = (torch.empty_like(sb["par"]), torch.empty_like(sb["cov"]))
+            launches.append(K.StepLauncher(g, sb["par"], sb["cov"], sb["hit_pos"], sb["hit_cov"], sb["layers"],
+                                           sb["bz"], sb["n"], out=outs, chi2=torch.empty(sb["n"], device="cuda"),
+                                           status=torch.empty(sb["n"], dtype=torch.int32, device="cuda"),
+                                           flags=args.flags, stream=stream))
+
+    def per_bucket():
+        for f in launches:
+            f()
+
+    if launches:
+        ms_b = time_launches(per_bucket, max(1, args.steps // 4), stream)
+    return {
+        "metric": METRIC,
+        "value": round(updates / (ms / 1e3), 1),
+        "unit": "track-layer updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.flags == 0 else "f32+f64", "data": "synthetic",
+        "config": {"workload": args.workload, "form": "persistent batched launch, hipGraph replay",
+                   "tracks": n, "updates_per_step": updates, "state_layout": args.layout,
+                   "block": args.block, "tracks_per_thread": args.tpt, "schedule": args.sched,
+                   "waves_mult": args.waves_mult, "ok_tracks": ok,
+                   "per_bucket_launches": len(launches), "per_bucket_ms": round(ms_b, 4),
+                   "per_bucket_updates_per_s": round(updates / (ms_b / 1e3), 1),
+                   "speedup_vs_per_bucket": round(ms_b / ms, 3)},
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,7 +152,12 @@ def main(argv=None):
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--tpt", type=int, default=1)
+    ap.add_argument("--sched", type=int, default=0, help="batched form: 0 dynamic queue, 1 static round-robin")
+    ap.add_argument("--waves-mult", type=int, default=1, help="batched form: grid in units of resident blocks")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
+    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched"],
+                    help="auto: batched for mixed-geometry workloads, plain otherwise")
     ap.add_argument("--cpu-tracks", type=int, default=480000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer --steps times (calibrates the HBM byte counters)")
@@ -100,10 +185,14 @@ def main(argv=None):
                           "copy_probe_bytes_written_per_call": dst.numel() * 4, "calls": args.steps}))
         return 0
     K.lib()
-    layout = parse_layout(args.layout)
     sample = S.generate(args.workload)
-    if sample["geom"].min() != sample["geom"].max():
-        raise SystemExit("bench.py times single-geometry workloads")
+    mixed = sample["geom"].min() != sample["geom"].max()
+    if args.form == "batched" or (args.form == "auto" and mixed):
+        print(json.dumps(bench_batched(args, sample)), flush=True)
+        return 0
+    if mixed:
+        raise SystemExit("the plain form needs a single-geometry workload")
+    layout = parse_layout(args.layout)
     geom = int(sample["geom"][0])
     st = K.stage_sample(sample, layout)
     n = st["n"]

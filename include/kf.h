@@ -40,9 +40,11 @@
  *                    elements per track; the buffer holds ceil(n/B) blocks
  *                    and the padding slots of the last block are neither read
  *                    nor written.
+ *   KF_AOS           track-major: offset i*E + e.
  *   Per-layer arrays (hits, checkpoints) add the layer l (0 <= l < n_layers):
  *     KF_SOA          offset (l*E + e)*n + i
  *     KF_AOSOA, B     offset ((i/B)*n_layers + l)*(E*B) + e*B + i%B
+ *     KF_AOS          offset (l*n + i)*E + e
  *   This is the array-of-structures-of-arrays organisation of Sec. 3.2 with a
  *   free batch width B.
  *
@@ -78,26 +80,39 @@ typedef enum {
   KF_E_UNSUPPORTED = 9 /* valid request this build does not implement */
 } kf_status_t;
 
-enum { KF_SOA = 0, KF_AOSOA = 1 };
+enum { KF_SOA = 0, KF_AOSOA = 1, KF_AOS = 2 };
 typedef struct {
-  int32_t kind;  /* KF_SOA or KF_AOSOA */
+  int32_t kind;  /* KF_SOA, KF_AOSOA or KF_AOS */
   int32_t block; /* AoSoA block width B; ignored for KF_SOA */
 } kf_layout_t;
 
-/* Launch shape; pass NULL for the built-in default.  block_threads in
- * {64, 128, 256}; tracks_per_thread in {1, 2} (a thread carries that many
- * tracks through the layer loop together). */
+/* Launch shape; pass NULL for the built-in default (256, 1, dynamic, 1).
+ *   block_threads      64, 128 or 256
+ *   tracks_per_thread  1 or 2; the plain kernels use 1 whatever is asked;
+ *                      the batched kernel gives each lane this many tracks of a
+ *                      work item, one after the other
+ *   schedule           batched kernel only: KF_SCHED_DYNAMIC (atomic work queue)
+ *                      or KF_SCHED_STATIC (round-robin over the waves)
+ *   waves_mult         batched kernel only: 1..8 (0 = 1), grid size in units
+ *                      of the blocks that fit on the GPU at once */
+enum { KF_SCHED_DYNAMIC = 0, KF_SCHED_STATIC = 1 };
 typedef struct {
   int32_t block_threads;
   int32_t tracks_per_thread;
+  int32_t schedule;
+  int32_t waves_mult;
 } kf_tune_t;
 
 /* flags */
 enum {
-  KF_F_FP64_INVERSE = 1u << 0, /* S = H P H^T + V, S^-1 and the gain K in FP64 */
-  KF_F_JOSEPH = 1u << 1        /* covariance update (I-KH) P (I-KH)^T + K V K^T, in FP64 */
+  KF_F_FP64_INVERSE = 1u << 0, /* S = H P H^T + V, S^-1, the gain K and the updates in FP64 */
+  KF_F_JOSEPH = 1u << 1,       /* as KF_F_FP64_INVERSE, and the covariance update in Joseph
+                                  form (I-KH) P (I-KH)^T + K V K^T */
+  KF_F_NO_GRAPH = 1u << 8      /* kf_propagate_update_batched only: enqueue the kernels
+                                  directly instead of replaying a cached hipGraph */
 };
 #define KF_F_PRECISION (KF_F_FP64_INVERSE | KF_F_JOSEPH)
+#define KF_BATCHED_MAX_TRACKS ((int64_t)2147483647 - 65536)
 
 /* per-track status word: flag bits, plus the number of layers applied in
  * bits 16..31 */
@@ -161,6 +176,50 @@ kf_status_t kf_propagate_update_r(
     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
     uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out,
     const kf_tune_t* tune, void* stream);
+
+/*
+ * kf_propagate_update_batched -- tracks of both geometries and uneven layer
+ * counts in one persistent launch (the paper's benchmarks give every track the
+ * same number of layers, Sec. 3.2; real events do not).
+ *
+ *   par_in .. cov_out   as kf_propagate_update_z, in `layout`
+ *   hit_pos, hit_cov    ragged per-track runs: track i's hit on its layer k
+ *                       (k < n_layers_per_track[i]) is row hit_offset[i] + k of
+ *                       hit_pos [H][3] and hit_cov [H][6]; every such row must exist
+ *   hit_offset          [n_tracks] int64, 8-byte aligned
+ *   geom                [n_tracks] uint8: 0 plane (layer_z), any other value cylinder (layer_r)
+ *   n_layers_per_track  [n_tracks] int32, clamped to [0, max_layers]
+ *   layer_z, layer_r    HOST [max_layers] each: layer k of a track is plane
+ *                       layer_z[k] or cylinder layer_r[k]
+ *   max_layers          0 .. KF_MAX_LAYERS
+ *   n_tracks            0 .. KF_BATCHED_MAX_TRACKS
+ *   flags               precision bits as kf_propagate_update_z, plus KF_F_NO_GRAPH
+ *   chi2_out, status_out  as kf_propagate_update_z
+ *   workspace           DEVICE scratch of at least kf_batched_workspace_size(n_tracks)
+ *                       bytes, 8-byte aligned, owned by the caller; calls that share a
+ *                       workspace must not overlap in time
+ *   tune                NULL or a launch shape (tracks_per_thread = tracks a lane
+ *                       takes from each work item)
+ *
+ * On the device each call sorts the tracks into work items of 64 (x
+ * tracks_per_thread) tracks with one geometry and one layer count, ordered by
+ * decreasing cost, and a grid that just fills the GPU pulls items from an
+ * atomic counter.  Unless KF_F_NO_GRAPH is set the five kernels of a call are
+ * captured once into a hipGraph, cached by the call's arguments (up to 32
+ * graphs), and replayed on `stream` by later identical calls -- so buffers
+ * passed once must stay valid while their graph is cached (kf_batched_release
+ * drops the cache).  Results per track are identical to
+ * kf_propagate_update_z / _r on the same track.
+ */
+int64_t kf_batched_workspace_size(int64_t n_tracks);
+kf_status_t kf_propagate_update_batched(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+    const float* hit_pos, const float* hit_cov, const int64_t* hit_offset, const uint8_t* geom,
+    const int32_t* n_layers_per_track, const float* layer_z, const float* layer_r, int32_t max_layers,
+    int64_t n_tracks, float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
+    int32_t* status_out, void* workspace, int64_t workspace_bytes, const kf_tune_t* tune, void* stream);
+/* Destroy every cached batched-call graph. */
+void kf_batched_release(void);
 
 /* Copy between KF_SOA and another layout for an array of n_elem elements per
  * track (n_layers_or_1 = 1 for per-track arrays, the layer count for

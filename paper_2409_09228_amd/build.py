@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkf.so")
-SOURCES = ["kf_api.hip", "kf_step.hip"]
-HEADERS = ["kf_device.h", "kf_internal.h", "kf_lanes.h"]
+SOURCES = ["kf_api.hip", "kf_step.hip", "kf_batched.hip"]
+HEADERS = ["kf_device.h", "kf_internal.h", "kf_lanes.h", "kf_track.h", "kf_batched.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -25,6 +25,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
+    "-Wl,--no-undefined",
     # never emit packed FP32 instructions (v_pk_fma_f32 and friends)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",

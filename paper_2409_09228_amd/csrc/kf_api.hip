@@ -2,9 +2,15 @@
 // dispatch to the kernel launchers.  Nothing here allocates device memory.
 #include <string.h>
 
+#include <list>
 #include <mutex>
+#include <string>
+#include <unordered_map>
+#include <utility>
 
+#include "kf_batched.h"
 #include "kf_internal.h"
+#include "kf_lanes.h"
 
 namespace {
 
@@ -13,14 +19,14 @@ constexpr double kCLight = 0.00299792458;
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 bool layout_ok(kf_layout_t lay, kf::TrackLayout* out) {
-  if (lay.kind == KF_SOA) {
-    *out = {0, 0};
+  if (lay.kind == KF_SOA || lay.kind == KF_AOS) {
+    *out = {lay.kind, 0};
     return true;
   }
   if (lay.kind != KF_AOSOA) return false;
   for (int sh = 4; sh <= 8; ++sh)
     if (lay.block == (1 << sh)) {
-      *out = {1, sh};
+      *out = {KF_AOSOA, sh};
       return true;
     }
   return false;
@@ -55,7 +61,10 @@ kf_status_t step(int geom, const float* par_in, const float* cov_in, float* par_
   if (tune) {
     block = tune->block_threads;
     tpt = tune->tracks_per_thread;
-    if ((block != 64 && block != 128 && block != 256) || (tpt != 1 && tpt != 2)) return KF_E_FLAGS;
+    if ((block != 64 && block != 128 && block != 256) || (tpt != 1 && tpt != 2) ||
+        (tune->schedule != KF_SCHED_DYNAMIC && tune->schedule != KF_SCHED_STATIC) || tune->waves_mult < 0 ||
+        tune->waves_mult > 8)
+      return KF_E_FLAGS;
   }
   if (geom == 1 && ckpt_out) return KF_E_UNSUPPORTED;
   if (n_tracks == 0) return KF_OK;
@@ -102,9 +111,146 @@ kf_status_t pack_common(const float* src, float* dst, int32_t n_elem, int32_t n_
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 
+// ------------------------------------------------------------ graph cache
+// Executable graphs of whole batched calls, keyed by every argument of the
+// call (pointers, sizes, tables, precision, launch shape) and the device.
+// Least recently used entries are destroyed beyond kMaxGraphs.
+constexpr size_t kMaxGraphs = 32;
+
+struct GraphCache {
+  std::mutex mu;
+  std::list<std::pair<std::string, hipGraphExec_t>> lru;  // front = most recent
+  std::unordered_map<std::string, std::list<std::pair<std::string, hipGraphExec_t>>::iterator> index;
+  hipStream_t capture[64] = {};
+};
+
+GraphCache& graphs() {
+  static GraphCache* g = new GraphCache();  // never destroyed: no HIP calls at exit
+  return *g;
+}
+
+kf_status_t batched_via_graph(const kf::BatchedArgs& a, int prec, int block, int dev, hipStream_t stream) {
+  std::string key(reinterpret_cast<const char*>(&a), sizeof(a));
+  key.append(reinterpret_cast<const char*>(&prec), sizeof(prec));
+  key.append(reinterpret_cast<const char*>(&block), sizeof(block));
+  key.append(reinterpret_cast<const char*>(&dev), sizeof(dev));
+  GraphCache& gc = graphs();
+  std::lock_guard<std::mutex> g(gc.mu);
+  hipGraphExec_t exec = nullptr;
+  auto it = gc.index.find(key);
+  if (it != gc.index.end()) {
+    gc.lru.splice(gc.lru.begin(), gc.lru, it->second);
+    exec = it->second->second;
+  } else {
+    if (!gc.capture[dev] && hipStreamCreateWithFlags(&gc.capture[dev], hipStreamNonBlocking) != hipSuccess)
+      return KF_E_LAUNCH;
+    hipStream_t cs = gc.capture[dev];
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return KF_E_LAUNCH;
+    const hipError_t le = kf::launch_batched(a, prec, block, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess || ce != hipSuccess || !graph) {
+      if (graph) hipGraphDestroy(graph);
+      return KF_E_LAUNCH;
+    }
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return KF_E_LAUNCH;
+    gc.lru.emplace_front(key, exec);
+    gc.index[key] = gc.lru.begin();
+    while (gc.lru.size() > kMaxGraphs) {
+      hipGraphExecDestroy(gc.lru.back().second);
+      gc.index.erase(gc.lru.back().first);
+      gc.lru.pop_back();
+    }
+  }
+  return hipGraphLaunch(exec, stream) == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
 }  // namespace
 
 extern "C" {
+
+int64_t kf_batched_workspace_size(int64_t n_tracks) {
+  return n_tracks < 0 ? 0 : kf::batched_workspace_bytes(n_tracks);
+}
+
+kf_status_t kf_propagate_update_batched(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out, const float* hit_pos,
+    const float* hit_cov, const int64_t* hit_offset, const uint8_t* geom, const int32_t* n_layers_per_track,
+    const float* layer_z, const float* layer_r, int32_t max_layers, int64_t n_tracks, float bz_tesla,
+    kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out, void* workspace,
+    int64_t workspace_bytes, const kf_tune_t* tune, void* stream) {
+  if (n_tracks < 0 || n_tracks > KF_BATCHED_MAX_TRACKS || max_layers < 0 || max_layers > KF_MAX_LAYERS)
+    return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  if (flags & ~uint32_t(KF_F_PRECISION | KF_F_NO_GRAPH)) return KF_E_FLAGS;
+  int block = 256, tpt = 1, sched = KF_SCHED_DYNAMIC, mult = 1;
+  if (tune) {
+    block = tune->block_threads;
+    tpt = tune->tracks_per_thread;
+    sched = tune->schedule;
+    mult = tune->waves_mult;
+    if ((block != 64 && block != 128 && block != 256) || (tpt != 1 && tpt != 2) ||
+        (sched != KF_SCHED_DYNAMIC && sched != KF_SCHED_STATIC) || mult < 0 || mult > 8)
+      return KF_E_FLAGS;
+    if (mult == 0) mult = 1;
+  }
+  if (n_tracks == 0) return KF_OK;
+  if (!par_in || !cov_in || !par_out || !cov_out || !geom || !n_layers_per_track || !hit_offset) return KF_E_NULL;
+  if (max_layers > 0 && (!hit_pos || !hit_cov || !layer_z || !layer_r)) return KF_E_NULL;
+  const void* ptrs[] = {par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, chi2_out, status_out, n_layers_per_track};
+  for (const void* p : ptrs)
+    if (p && !aligned4(p)) return KF_E_ALIGN;
+  if ((reinterpret_cast<uintptr_t>(hit_offset) & 7u) || (reinterpret_cast<uintptr_t>(workspace) & 7u))
+    return KF_E_ALIGN;
+  kf::BatchedArgs a;
+  memset(&a, 0, sizeof(a));  // the bytes of `a` key the graph cache
+  if (!kf::batched_carve(workspace, workspace_bytes, n_tracks, &a.ws)) return KF_E_WORKSPACE;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  a.par_in = par_in;
+  a.cov_in = cov_in;
+  a.par_out = par_out;
+  a.cov_out = cov_out;
+  a.hit_pos = hit_pos;
+  a.hit_cov = hit_cov;
+  a.hit_offset = hit_offset;
+  a.geom = geom;
+  a.nlay = n_layers_per_track;
+  a.chi2 = chi2_out;
+  a.status = status_out;
+  a.n = n_tracks;
+  a.L = max_layers;
+  a.tpt = tpt;
+  a.schedule = sched;
+  a.waves_mult = mult;
+  a.lay = tl;
+  a.b = float(kCLight * double(bz_tesla));
+  kf::bucket_order(a.order);
+  for (int l = 0; l < max_layers; ++l) {
+    a.layer_z[l] = layer_z[l];
+    a.layer_r[l] = layer_r[l];
+  }
+  const int prec = (flags & KF_F_JOSEPH) ? 2 : ((flags & KF_F_FP64_INVERSE) ? 1 : 0);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (flags & KF_F_NO_GRAPH) {
+    const hipError_t e = kf::launch_batched(a, prec, block, st);
+    return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KF_E_DEVICE;
+  return batched_via_graph(a, prec, block, dev, st);
+}
+
+void kf_batched_release(void) {
+  GraphCache& gc = graphs();
+  std::lock_guard<std::mutex> g(gc.mu);
+  for (auto& e : gc.lru) hipGraphExecDestroy(e.second);
+  gc.lru.clear();
+  gc.index.clear();
+}
 
 kf_status_t kf_propagate_update_z(const float* par_in, const float* cov_in, float* par_out, float* cov_out,
                                   const float* hit_pos, const float* hit_cov, const float* layer_z,
@@ -137,9 +283,7 @@ kf_status_t kf_unpack(const float* src, float* dst_soa, int32_t n_elem, int32_t 
 int64_t kf_array_floats(int32_t n_elem, int32_t n_layers_or_1, int64_t n_tracks, kf_layout_t layout) {
   kf::TrackLayout tl;
   if (n_elem <= 0 || n_layers_or_1 <= 0 || n_tracks < 0 || !layout_ok(layout, &tl)) return 0;
-  if (!tl.aos) return int64_t(n_elem) * n_layers_or_1 * n_tracks;
-  const int64_t B = int64_t(1) << tl.shift;
-  return ((n_tracks + B - 1) / B) * B * n_elem * n_layers_or_1;
+  return kf::layout_floats(n_tracks, n_elem, n_layers_or_1, tl);
 }
 
 const char* kf_status_string(kf_status_t s) {

@@ -1,0 +1,287 @@
+// Mixed-geometry, uneven-length batches: one persistent launch.
+//
+// Planning, on the device, every call (so the whole call can be captured once
+// into a hipGraph and replayed):
+//   1. clear      zero the bucket counters and the work counter
+//   2. count      histogram of tracks over buckets (geometry, layer count)
+//   3. scan       lay the buckets out in decreasing estimated cost (layer
+//                 count, with a cylinder layer costing about twice a plane
+//                 layer), each rounded up to whole work items of W = 64 *
+//                 tracks_per_thread tracks; one bucket id per item (slots past
+//                 a bucket's count are skipped)
+//   4. scatter    track indices into their bucket's slots
+//   5. run        persistent waves claim items from an atomic counter, longest
+//                 first; an item holds tracks of one geometry and one layer
+//                 count, so a wave never diverges on either.
+// A work item's tracks are gathered by index: their state through the track
+// layout, their hits from ragged per-track runs.
+#include "kf_batched.h"
+#include "kf_lanes.h"
+#include "kf_track.h"
+
+namespace kf {
+
+__host__ __device__ inline int bucket_of(uint8_t geom, int nl, int max_layers) {
+  const int g = geom ? 1 : 0;
+  const int l = nl < 0 ? 0 : (nl > max_layers ? max_layers : nl);
+  return g * (KF_MAX_LAYERS + 1) + l;
+}
+
+__global__ void __launch_bounds__(256) kf_plan_clear(BatchedArgs a) {
+  for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) {
+    a.ws.bucket_count[b] = 0;
+    a.ws.bucket_cursor[b] = 0;
+  }
+  if (threadIdx.x < 4) a.ws.counter[threadIdx.x] = 0;
+}
+
+// Per-block histograms in LDS, one global atomic per (block, bucket).
+__global__ void __launch_bounds__(256) kf_plan_count(BatchedArgs a) {
+  __shared__ int hist[KF_NBUCKETS];
+  for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&hist[bucket_of(a.geom[i], a.nlay[i], a.L)], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x)
+    if (hist[b]) atomicAdd(&a.ws.bucket_count[b], hist[b]);
+}
+
+// One block.  Buckets in the order given by a.order (decreasing cost); the
+// counts are read in parallel into LDS, scanned there, and every item's
+// bucket id is written in parallel (binary search over the item bases).
+__global__ void __launch_bounds__(256) kf_plan_scan(BatchedArgs a) {
+  __shared__ int cnt[KF_NBUCKETS];
+  __shared__ int base_item[KF_NBUCKETS + 1];
+  const int W = 64 * a.tpt;
+  const int wsh = a.tpt == 2 ? 7 : 6;  // log2(W)
+  for (int j = threadIdx.x; j < KF_NBUCKETS; j += blockDim.x) cnt[j] = a.ws.bucket_count[a.order[j]];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int items = 0;
+    for (int j = 0; j < KF_NBUCKETS; ++j) {
+      base_item[j] = items;
+      items += (cnt[j] + W - 1) >> wsh;
+    }
+    base_item[KF_NBUCKETS] = items;
+    a.ws.counter[1] = items;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < KF_NBUCKETS; j += blockDim.x) a.ws.bucket_base[a.order[j]] = base_item[j] * W;
+  const int n_items = base_item[KF_NBUCKETS];
+  for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
+    int lo = 0, hi = KF_NBUCKETS - 1;  // last j with base_item[j] <= it
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (base_item[mid] <= it) lo = mid; else hi = mid - 1;
+    }
+    a.ws.item_bucket[it] = a.order[lo];
+  }
+}
+
+// Track indices into their bucket's slots: ranks within the block from LDS
+// atomics, one global atomic per (block, bucket) to reserve the range.
+__global__ void __launch_bounds__(256) kf_plan_scatter(BatchedArgs a) {
+  constexpr int kPer = 4;  // tracks per thread
+  __shared__ int local[KF_NBUCKETS];
+  __shared__ int start[KF_NBUCKETS];
+  for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) local[b] = 0;
+  __syncthreads();
+  int bk[kPer], rk[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = (int64_t(blockIdx.x) * kPer + u) * blockDim.x + threadIdx.x;
+    bk[u] = -1;
+    if (i < a.n) {
+      bk[u] = bucket_of(a.geom[i], a.nlay[i], a.L);
+      rk[u] = atomicAdd(&local[bk[u]], 1);
+    }
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < KF_NBUCKETS; c += blockDim.x)
+    start[c] = local[c] ? atomicAdd(&a.ws.bucket_cursor[c], local[c]) : 0;
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = (int64_t(blockIdx.x) * kPer + u) * blockDim.x + threadIdx.x;
+    if (bk[u] >= 0) a.ws.perm[a.ws.bucket_base[bk[u]] + start[bk[u]] + rk[u]] = int32_t(i);
+  }
+}
+
+// ---------------------------------------------------------------- the run
+template <int KIND, bool WIDE>
+struct GatherState {
+  const BatchedArgs& a;
+  const Lanes<KIND, WIDE>& ln;
+  __device__ __forceinline__ bool load(float p[6], float C[21]) const {
+    ln.template ld_all<6>(ln.par, a.par_in, 0, p);
+    ln.template ld_all<21>(ln.cov, a.cov_in, 0, C);
+    bool ok = true;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) ok = ok & fin(p[e]);
+#pragma unroll
+    for (int e = 0; e < 21; ++e) ok = ok & fin(C[e]);
+    return ok;
+  }
+  __device__ __forceinline__ void store(const float p[6], const float C[21]) const {
+    ln.template st_all<6>(ln.par, a.par_out, 0, p);
+    ln.template st_all<21>(ln.cov, a.cov_out, 0, C);
+  }
+};
+
+// hits of a track: rows hit_offset[t] .. hit_offset[t] + n_layers - 1 of the
+// ragged [H][3] and [H][6] arrays
+struct RaggedHits {
+  const float* hp;
+  const float* hc;
+  __device__ __forceinline__ void load(int k, float m[3], float V[6]) const {
+    ld_rec<3>(hp + 3 * k, m);
+    ld_rec<6>(hc + 6 * k, V);
+  }
+  __device__ __forceinline__ int next(int k, int nl) const { return k + 1 < nl ? k + 1 : k; }
+};
+
+template <int PREC, int KIND, bool WIDE>
+__device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geom, int nl) {
+  const Lanes<KIND, WIDE> ln(t, a.n, 1, a.lay);
+  const int64_t h0 = a.hit_offset[t];
+  const RaggedHits hits{a.hit_pos + h0 * 3, a.hit_cov + h0 * 6};
+  float chi2;
+  uint32_t status;
+  if (geom == 0)
+    run_track<0, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_z, a.b, chi2, status);
+  else
+    run_track<1, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_r, a.b, chi2, status);
+  if (a.chi2) a.chi2[t] = chi2;
+  if (a.status) a.status[t] = int32_t(status);
+}
+
+// Every wave loops over work items until the items run out -- which every
+// wave reaches, item numbers only grow.  Schedules:
+//   KF_SCHED_DYNAMIC  first item = the wave's number, then lane 0 claims the
+//                     next one from an atomic counter (broadcast to the wave)
+//   KF_SCHED_STATIC   items wave, wave + n_waves, wave + 2 n_waves, ...
+//                     (no atomics; the items are already longest-first)
+template <int PREC, int KIND, bool WIDE>
+__global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int W = 64 * a.tpt;
+  const int n_waves = int(gridDim.x * (blockDim.x >> 6));
+  const int n_items = a.ws.counter[1];
+  int item = int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  while (item < n_items) {
+    const int b = a.ws.item_bucket[item];
+    const int geom = b / (KF_MAX_LAYERS + 1);
+    const int nl = b % (KF_MAX_LAYERS + 1);
+    const int64_t slot0 = int64_t(item) * W;
+    const int64_t end = int64_t(a.ws.bucket_base[b]) + a.ws.bucket_count[b];  // first slot past the bucket
+    for (int u = 0; u < a.tpt; ++u) {
+      const int64_t slot = slot0 + u * 64 + lane;
+      if (slot < end) run_one<PREC, KIND, WIDE>(a, a.ws.perm[slot], geom, nl);
+    }
+    if (a.schedule == KF_SCHED_STATIC) {
+      item += n_waves;
+    } else {
+      int next = 0;
+      if (lane == 0) next = atomicAdd(&a.ws.counter[0], 1);
+      item = n_waves + __shfl(next, 0, 64);
+    }
+  }
+}
+
+// Enough waves to fill every CU at the kernel's occupancy, no more.
+template <int PREC, int KIND, bool WIDE>
+static hipError_t launch_run(const BatchedArgs& a, int block, hipStream_t s) {
+  int dev = 0, n_cu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
+    return hipErrorInvalidDevice;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf_batched_kernel<PREC, KIND, WIDE>, block, 0) !=
+          hipSuccess ||
+      per_cu <= 0)
+    per_cu = 1;
+  const int mult = a.waves_mult > 0 ? a.waves_mult : 1;
+  hipLaunchKernelGGL((kf_batched_kernel<PREC, KIND, WIDE>), dim3(unsigned(per_cu * n_cu * mult)), dim3(block), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_kinds(const BatchedArgs& a, int block, bool wide, hipStream_t s) {
+  if (a.lay.kind == KF_AOS)
+    return wide ? launch_run<PREC, KF_AOS, true>(a, block, s) : launch_run<PREC, KF_AOS, false>(a, block, s);
+  if (a.lay.kind == KF_AOSOA)
+    return wide ? launch_run<PREC, KF_AOSOA, true>(a, block, s) : launch_run<PREC, KF_AOSOA, false>(a, block, s);
+  return wide ? launch_run<PREC, KF_SOA, true>(a, block, s) : launch_run<PREC, KF_SOA, false>(a, block, s);
+}
+
+hipError_t launch_batched(const BatchedArgs& a, int prec, int block, hipStream_t s) {
+  const int64_t blocks = (a.n + 255) / 256;
+  const unsigned g_count = unsigned(blocks < 1 ? 1 : (blocks > 256 ? 256 : blocks));
+  const unsigned g_scatter = unsigned((a.n + 1023) / 1024 > 0 ? (a.n + 1023) / 1024 : 1);
+  hipLaunchKernelGGL(kf_plan_clear, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(kf_plan_count, dim3(g_count), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(kf_plan_scan, dim3(1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(kf_plan_scatter, dim3(g_scatter), dim3(256), 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const bool wide = needs_wide(a.n, 1, a.lay);
+  if (prec == 0) return launch_kinds<PREC_F32>(a, block, wide, s);
+  if (prec == 1) return launch_kinds<PREC_F64>(a, block, wide, s);
+  return launch_kinds<PREC_F64_JOSEPH>(a, block, wide, s);
+}
+
+// Order of buckets by decreasing estimated cost: layers x (2 for cylinders).
+void bucket_order(int32_t order[KF_NBUCKETS]) {
+  int cost[KF_NBUCKETS];
+  for (int b = 0; b < KF_NBUCKETS; ++b) {
+    order[b] = b;
+    cost[b] = (b % (KF_MAX_LAYERS + 1)) * (b / (KF_MAX_LAYERS + 1) ? 2 : 1);
+  }
+  // insertion sort, stable: equal costs keep plane buckets first
+  for (int i = 1; i < KF_NBUCKETS; ++i) {
+    const int v = order[i];
+    int j = i - 1;
+    while (j >= 0 && cost[order[j]] < cost[v]) {
+      order[j + 1] = order[j];
+      --j;
+    }
+    order[j + 1] = v;
+  }
+}
+
+}  // namespace kf
+
+namespace kf {
+
+static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+static void sizes(int64_t n, int64_t* items, int64_t* slots) {
+  *items = (n + 63) / 64 + KF_NBUCKETS;           // most items: 64-track items
+  *slots = n + int64_t(KF_NBUCKETS + 1) * 128;    // most slots: 128-track items
+}
+
+int64_t batched_workspace_bytes(int64_t n) {
+  int64_t items, slots;
+  sizes(n, &items, &slots);
+  return align256(4 * (3 * KF_NBUCKETS + 4)) + align256(4 * items) + align256(4 * slots);
+}
+
+bool batched_carve(void* ws, int64_t bytes, int64_t n, BatchedWorkspace* out) {
+  if (!ws || bytes < batched_workspace_bytes(n)) return false;
+  int64_t items, slots;
+  sizes(n, &items, &slots);
+  char* p = static_cast<char*>(ws);
+  int32_t* head = reinterpret_cast<int32_t*>(p);
+  out->bucket_count = head;
+  out->bucket_cursor = head + KF_NBUCKETS;
+  out->bucket_base = head + 2 * KF_NBUCKETS;
+  out->counter = head + 3 * KF_NBUCKETS;
+  p += align256(4 * (3 * KF_NBUCKETS + 4));
+  out->item_bucket = reinterpret_cast<int32_t*>(p);
+  p += align256(4 * items);
+  out->perm = reinterpret_cast<int32_t*>(p);
+  return true;
+}
+
+}  // namespace kf

@@ -9,11 +9,9 @@
 
 namespace kf {
 
-// Where track i's element e (of E per track, layer l of L) sits:
-//   base(E, L) + (l * E + e) * es
-// SoA: blk = 0, lane = i, es = n.  AoSoA-B: blk = i / B, lane = i % B, es = B.
+// Physical layout of a launch's track arrays (see kf_lanes.h).
 struct TrackLayout {
-  int32_t aos;   // 0 SoA, 1 AoSoA
+  int32_t kind;  // KF_SOA, KF_AOSOA or KF_AOS
   int32_t shift; // log2(B) for AoSoA
 };
 

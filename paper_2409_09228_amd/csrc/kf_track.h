@@ -1,0 +1,84 @@
+// The per-track layer loop shared by the plain and the persistent kernels.
+//
+// A lane owns one track: it reads the 27-number state once, runs every layer
+// with the state in registers, and writes it once.  The loop updates the
+// state in place, so the pre-layer state is never kept alive in registers
+// for the failure path; a track that fails at layer k (rare) re-reads its
+// input -- untouched until the final store, also when the call is in place --
+// and re-applies layers 0..k-1 after the loop.
+#pragma once
+
+#include "kf_device.h"
+
+namespace kf {
+
+// One layer: propagate to surface `target`, transport the covariance, update
+// with hit (m, V).  On success the state (p, C) and chi2 advance in place and 0
+// is returned; otherwise the status bits, with (p, C) left undefined.
+template <int GEOM, int PREC>
+__device__ __forceinline__ uint32_t layer_step(float p[6], float C[21], const float m[3], const float V[6],
+                                               float target, float b, float& chi2) {
+  float q[6], Pt[21];
+  const uint32_t fp = propagate<GEOM>(p, C, target, b, q, Pt);
+  float dchi;
+  const uint32_t fu = update<GEOM, PREC>(q, Pt, m, V, dchi);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) p[e] = q[e];
+#pragma unroll
+  for (int e = 0; e < 21; ++e) C[e] = Pt[e];
+  chi2 += dchi;
+  return fp ? fp : fu;
+}
+
+// IO concepts used below:
+//   state.load(p, C) -> bool all-finite;  state.store(p, C)
+//   hits.load(k, m, V): hit of layer k (k < n_layers of the launch);
+//   hits.next(k): the layer index to prefetch after layer k (in bounds)
+//   ckpt(k, p, C): called before layer k (may do nothing)
+struct NoCkpt {
+  __device__ __forceinline__ void operator()(int, const float*, const float*) const {}
+};
+
+template <int GEOM, int PREC, class State, class Hits, class Ckpt>
+__device__ __forceinline__ void run_track(const State& state, const Hits& hits, const Ckpt& ckpt, int nl,
+                                          const float* layer, float b, float& chi2_out, uint32_t& status_out) {
+  float p[6], C[21];
+  uint32_t flags = state.load(p, C) ? 0u : S_NONFINITE;
+  float chi2 = 0.0f;
+  int k = 0;
+  if (!flags && nl > 0) {
+    // hits of the next layer are fetched one layer ahead
+    float mn[3], Vn[6];
+    hits.load(0, mn, Vn);
+    for (; k < nl; ++k) {
+      float m[3], V[6];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) m[e] = mn[e];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) V[e] = Vn[e];
+      hits.load(hits.next(k, nl), mn, Vn);
+      ckpt(k, p, C);
+      const uint32_t f = layer_step<GEOM, PREC>(p, C, m, V, layer[k], b, chi2);
+      if (f) {
+        flags = f;
+        break;
+      }
+    }
+  }
+  const int done = k;
+  if (flags) {
+    // recompute the state from before the failing layer
+    state.load(p, C);
+    chi2 = 0.0f;
+    for (int j = 0; j < done; ++j) {
+      float m[3], V[6];
+      hits.load(j, m, V);
+      layer_step<GEOM, PREC>(p, C, m, V, layer[j], b, chi2);
+    }
+  }
+  state.store(p, C);
+  chi2_out = chi2;
+  status_out = flags | (uint32_t(done) << KF_S_LAYERS_SHIFT);
+}
+
+}  // namespace kf

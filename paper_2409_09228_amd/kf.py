@@ -26,6 +26,8 @@ KF_AOSOA = 1
 KF_F_FP64_INVERSE = 1
 KF_F_JOSEPH = 2
 KF_F_PRECISION = 3
+KF_F_NO_GRAPH = 256
+KF_AOS = 2
 KF_MAX_LAYERS = 64
 S_NONFINITE = 1
 S_NOT_PD = 2
@@ -45,10 +47,22 @@ class Layout(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("block_threads", ctypes.c_int32), ("tracks_per_thread", ctypes.c_int32)]
+    _fields_ = [("block_threads", ctypes.c_int32), ("tracks_per_thread", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("waves_mult", ctypes.c_int32)]
+
+
+SCHED_DYNAMIC = 0
+SCHED_STATIC = 1
+
+
+def make_tune(tune):
+    """(block, tracks_per_thread[, schedule[, waves_mult]]) -> Tune."""
+    t = tuple(int(x) for x in tune) + (0, 1)[len(tune) - 2:] if len(tune) < 4 else tuple(int(x) for x in tune)
+    return Tune(*t[:4])
 
 
 SOA = (KF_SOA, 0)
+AOS = (KF_AOS, 0)
 
 
 def aosoa(block: int):
@@ -76,6 +90,12 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [vp, vp, i32, i32, i64, Layout, vp]
             fn.restype = ctypes.c_int
+        L.kf_batched_workspace_size.argtypes = [i64]
+        L.kf_batched_workspace_size.restype = i64
+        L.kf_propagate_update_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, f32, Layout,
+                                                  ctypes.c_uint32, vp, vp, vp, i64, ctypes.POINTER(Tune), vp]
+        L.kf_propagate_update_batched.restype = ctypes.c_int
+        L.kf_batched_release.restype = None
         L.kf_array_floats.argtypes = [i32, i32, i64, Layout]
         L.kf_array_floats.restype = ctypes.c_int64
         L.kf_status_string.argtypes = [ctypes.c_int]
@@ -128,6 +148,8 @@ def empty_like_layout(n_elem: int, n_layers: int, n: int, layout, device="cuda")
     kind, B = layout
     if kind == KF_SOA:
         shape = (n_elem, n) if n_layers == 1 else (n_layers, n_elem, n)
+    elif kind == KF_AOS:
+        shape = (n, n_elem) if n_layers == 1 else (n_layers, n, n_elem)
     else:
         nb = (n + B - 1) // B
         shape = (nb, n_elem, B) if n_layers == 1 else (nb, n_layers, n_elem, B)
@@ -158,7 +180,7 @@ def propagate_update(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n
         c2 = None
     if st is False:
         st = None
-    tn = None if tune is None else ctypes.byref(Tune(int(tune[0]), int(tune[1])))
+    tn = None if tune is None else ctypes.byref(make_tune(tune))
     fn = lib().kf_propagate_update_z if geom == 0 else lib().kf_propagate_update_r
     with torch.cuda.device(dev):
         rc = fn(_ptr(par), _ptr(cov), _ptr(par_out), _ptr(cov_out), _ptr(hit_pos), _ptr(hit_cov),
@@ -182,7 +204,7 @@ class StepLauncher:
         _require_cuda(par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, *out)
         self._layers = np.ascontiguousarray(layers, np.float32)
         self._keep = (par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, out)
-        self._tune = None if tune is None else Tune(int(tune[0]), int(tune[1]))
+        self._tune = None if tune is None else make_tune(tune)
         self._fn = lib().kf_propagate_update_z if geom == 0 else lib().kf_propagate_update_r
         self._name = "kf_propagate_update_z" if geom == 0 else "kf_propagate_update_r"
         self._device = par.device
@@ -246,6 +268,15 @@ def to_soa_tensor(arr: np.ndarray, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device)
 
 
+def from_layout(t, n_elem: int, n: int, layout) -> np.ndarray:
+    """A per-track array in `layout` -> logical numpy [n, n_elem]."""
+    if layout[0] == KF_AOS:
+        return t.detach().cpu().numpy().reshape(n, n_elem)
+    if layout[0] != KF_SOA:
+        t = unpack(t, n_elem, 1, n, layout)
+    return from_soa_tensor(t)
+
+
 def from_soa_tensor(t) -> np.ndarray:
     """Inverse of to_soa_tensor, as a numpy array."""
     a = t.detach().cpu().numpy()
@@ -270,6 +301,11 @@ def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
     out["layers"] = np.asarray(sample["layer_z"] if geom == 0 else sample["layer_r"], np.float32)[:L]
     if layout[0] == KF_SOA:
         out.update(soa)
+    elif layout[0] == KF_AOS:
+        out["par"] = torch.from_numpy(np.ascontiguousarray(sample["par"], np.float32)).to(device)
+        out["cov"] = torch.from_numpy(np.ascontiguousarray(sample["cov"], np.float32)).to(device)
+        out["hit_pos"] = torch.from_numpy(np.ascontiguousarray(sample["hit_pos"], np.float32)).to(device)
+        out["hit_cov"] = torch.from_numpy(np.ascontiguousarray(sample["hit_cov"], np.float32)).to(device)
     else:
         out["par"] = pack(soa["par"], 6, 1, n, layout)
         out["cov"] = pack(soa["cov"], 21, 1, n, layout)
@@ -289,7 +325,82 @@ def results_to_logical(st: dict, par_out, cov_out):
     """Device results in the staged layout -> logical numpy [n, 6], [n, 21] (float64)."""
     n = st["n"]
     lay = st["layout"]
-    if lay[0] != KF_SOA:
-        par_out = unpack(par_out, 6, 1, n, lay)
-        cov_out = unpack(cov_out, 21, 1, n, lay)
-    return from_soa_tensor(par_out).astype(np.float64), from_soa_tensor(cov_out).astype(np.float64)
+    return (from_layout(par_out, 6, n, lay).astype(np.float64), from_layout(cov_out, 21, n, lay).astype(np.float64))
+
+
+# ----------------------------------------------------------------------------
+# mixed geometry, uneven layer counts: one persistent launch
+def batched_workspace(n: int, device="cuda"):
+    import torch
+    return torch.empty(int(lib().kf_batched_workspace_size(int(n))), dtype=torch.uint8, device=device)
+
+
+class BatchedLauncher:
+    """A kf_propagate_update_batched call with every argument converted once."""
+
+    def __init__(self, st: dict, out, chi2, status, flags: int = 0, tune=None, stream=None, workspace=None):
+        import torch
+        n = st["n"]
+        _require_cuda(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["hit_offset"], st["geom"],
+                      st["nlay"], chi2, status, *out)
+        self._ws = batched_workspace(n, st["par"].device) if workspace is None else workspace
+        self._lz = np.ascontiguousarray(st["layer_z"], np.float32)
+        self._lr = np.ascontiguousarray(st["layer_r"], np.float32)
+        self._keep = (st, out, chi2, status)
+        self._tune = None if tune is None else make_tune(tune)
+        with torch.cuda.device(st["par"].device):
+            sp = _stream(stream)
+        self._args = (_ptr(st["par"]), _ptr(st["cov"]), _ptr(out[0]), _ptr(out[1]), _ptr(st["hit_pos"]),
+                      _ptr(st["hit_cov"]), _ptr(st["hit_offset"]), _ptr(st["geom"]), _ptr(st["nlay"]),
+                      self._lz.ctypes.data_as(ctypes.c_void_p), self._lr.ctypes.data_as(ctypes.c_void_p),
+                      int(st["L"]), int(n), float(st["bz"]), Layout(*st["layout"]), int(flags), _ptr(chi2),
+                      _ptr(status), _ptr(self._ws), int(self._ws.numel()),
+                      None if self._tune is None else ctypes.byref(self._tune), sp)
+
+    def __call__(self):
+        rc = lib().kf_propagate_update_batched(*self._args)
+        if rc != KF_OK:
+            raise KFError(rc, "kf_propagate_update_batched")
+
+
+def stage_batched(sample: dict, layout=AOS, device="cuda") -> dict:
+    """Upload a mixed sample: track state in `layout`, hits as ragged runs."""
+    import torch
+    from . import synth
+    n = sample["par"].shape[0]
+    L = sample["hit_pos"].shape[0]
+    hp, hc, off = synth.to_ragged(sample["hit_pos"], sample["hit_cov"], sample["nlay"])
+    soa_par = to_soa_tensor(sample["par"], device)
+    soa_cov = to_soa_tensor(sample["cov"], device)
+    if layout[0] == KF_SOA:
+        par, cov = soa_par, soa_cov
+    else:
+        par, cov = pack(soa_par, 6, 1, n, layout), pack(soa_cov, 21, 1, n, layout)
+    dev = torch.device(device)
+    return {
+        "n": n, "L": L, "layout": layout, "bz": float(sample["bz"]),
+        "par": par, "cov": cov,
+        "hit_pos": torch.from_numpy(np.ascontiguousarray(hp, np.float32).reshape(-1, 3)).to(dev),
+        "hit_cov": torch.from_numpy(np.ascontiguousarray(hc, np.float32).reshape(-1, 6)).to(dev),
+        "hit_offset": torch.from_numpy(off.astype(np.int64)).to(dev),
+        "geom": torch.from_numpy(np.ascontiguousarray(sample["geom"], np.uint8)).to(dev),
+        "nlay": torch.from_numpy(np.ascontiguousarray(sample["nlay"], np.int32)).to(dev),
+        "layer_z": np.asarray(sample["layer_z"], np.float32)[:L],
+        "layer_r": np.asarray(sample["layer_r"], np.float32)[:L],
+    }
+
+
+def run_batched(st: dict, flags: int = 0, tune=None, stream=None, workspace=None):
+    """One batched call on a staged mixed sample; returns (par_out, cov_out, chi2, status)."""
+    import torch
+    par_out = torch.empty_like(st["par"])
+    cov_out = torch.empty_like(st["cov"])
+    chi2 = torch.empty(st["n"], dtype=torch.float32, device=st["par"].device)
+    status = torch.empty(st["n"], dtype=torch.int32, device=st["par"].device)
+    BatchedLauncher(st, (par_out, cov_out), chi2, status, flags=flags, tune=tune, stream=stream,
+                    workspace=workspace)()
+    return par_out, cov_out, chi2, status
+
+
+def release_graphs():
+    lib().kf_batched_release()
