@@ -178,6 +178,35 @@ kf_status_t kf_propagate_update_r(
     const kf_tune_t* tune, void* stream);
 
 /*
+ * kf_chi2_backward_z -- adjoint of L = sum_i grad_chi2[i] * chi2_i for the plane
+ * filter (kf_propagate_update_z in FP32, flags 0): dL/d(hit positions),
+ * dL/d(seed parameters) and, optionally, dL/d(seed covariance).  chi2_i sums
+ * r^T S^-1 r over the layers track i applied (the paper's step, Sec. 3.2;
+ * the chi-square itself is this project's addition).  The derivative is the
+ * full one, including the covariance's dependence on the parameters through
+ * the Jacobian (whose own derivative is taken by dual numbers).
+ *
+ *   par_in .. n_tracks, bz_tesla, layout   the forward call's inputs
+ *   status_fwd     [n_tracks] the forward's status words: track i's
+ *                  gradient runs over its first (status >> 16) layers
+ *   ckpt           the forward's ckpt_out, or NULL to recompute the entering
+ *                  state of every layer from the seed (no extra memory,
+ *                  O(layers^2) work instead of O(layers))
+ *   grad_chi2      [n_tracks] dL/dchi2_i
+ *   grad_hit_pos   per-layer [n_layers][3] in `layout`; layers a track did not
+ *                  apply get 0
+ *   grad_par_in    [6] per track in `layout`
+ *   grad_cov_in    [21] per track in `layout`, or NULL
+ */
+kf_status_t kf_chi2_backward_z(
+    const float* par_in, const float* cov_in, const float* hit_pos, const float* hit_cov,
+    const float* layer_z, int32_t n_layers, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
+    const int32_t* status_fwd, const float* ckpt, const float* grad_chi2, float* grad_hit_pos,
+    float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream);
+/* Floats of a checkpoint buffer for kf_propagate_update_z / kf_chi2_backward_z. */
+int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t layout);
+
+/*
  * kf_propagate_update_batched -- tracks of both geometries and uneven layer
  * counts in one persistent launch (the paper's benchmarks give every track the
  * same number of layers, Sec. 3.2; real events do not).

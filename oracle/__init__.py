@@ -50,7 +50,9 @@ def lib():
         L.kfo_propagate.argtypes = [c_int, d, c_dbl, c_dbl, d, d, u32]
         L.kfo_update.argtypes = [d, d, d, d, c_int, d, d, d, u32]
         L.kfo_grad_chi2.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, c_int]
-        for fn in (L.kfo_run_f64, L.kfo_run_f32, L.kfo_propagate, L.kfo_update, L.kfo_grad_chi2):
+        L.kfo_grad_chi2_f32.argtypes = L.kfo_grad_chi2.argtypes
+        for fn in (L.kfo_run_f64, L.kfo_run_f32, L.kfo_propagate, L.kfo_update, L.kfo_grad_chi2,
+                   L.kfo_grad_chi2_f32):
             fn.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -133,8 +135,9 @@ def update(p, P21, m, V6, joseph=False):
 
 
 def grad_chi2(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, w=None, nlay=None,
-              joseph=False, nthreads=None):
-    """Reference gradient of sum_i w_i chi2_i: (g_hit [L, n, 3], g_par [n, 6])."""
+              joseph=False, nthreads=None, precision: str = "f64"):
+    """Reference gradient of sum_i w_i chi2_i: (g_hit [L, n, 3], g_par [n, 6]).
+    precision="f32" evaluates the same algorithm in float (tolerance sizing)."""
     par = np.ascontiguousarray(par, np.float64)
     cov = np.ascontiguousarray(cov, np.float64)
     hit_pos = np.ascontiguousarray(hit_pos, np.float64)
@@ -146,7 +149,8 @@ def grad_chi2(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, w=None, 
     nl = None if nlay is None else np.ascontiguousarray(nlay, np.int32)
     gh = np.zeros((L, n, 3))
     gp = np.zeros((n, 6))
-    rc = lib().kfo_grad_chi2(int(geom), n, L, _p(layers, ctypes.c_double), float(bz),
+    fn = lib().kfo_grad_chi2 if precision == "f64" else lib().kfo_grad_chi2_f32
+    rc = fn(int(geom), n, L, _p(layers, ctypes.c_double), float(bz),
                              _p(nl, ctypes.c_int32), _p(par, ctypes.c_double), _p(cov, ctypes.c_double),
                              _p(hit_pos, ctypes.c_double), _p(hit_cov, ctypes.c_double),
                              int(bool(joseph)), _p(w, ctypes.c_double), _p(gh, ctypes.c_double),

@@ -411,12 +411,15 @@ void run_batch(int geom, int64_t n, int L, const double* layers, double bz, cons
 // Reference gradient of sum_i w_i chi2_i with respect to the seed parameters
 // and the hit positions, by forward-mode dual numbers through the whole
 // chain (the Jacobian's own dependence on p enters through nested duals).
+// Instantiated in double (the reference) and in float (only to size the
+// tolerance of a float-arithmetic gradient); inputs and outputs are double.
 constexpr int kGradChunk = 6;
+template <class R>
 void grad_batch(int geom, int64_t n, int L, const double* layers, double bz, const int32_t* nlay,
                 const double* par_in, const double* cov_in, const double* hit_pos,
                 const double* hit_cov, int joseph, const double* w, double* g_hit, double* g_par,
                 int nthreads) {
-  using D = Dual<double, kGradChunk>;
+  using D = Dual<R, kGradChunk>;
   const double b = kCLight * bz;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -441,24 +444,24 @@ void grad_batch(int geom, int64_t n, int L, const double* layers, double bz, con
       for (int c0 = 0; c0 < nin; c0 += kGradChunk) {
         V6<D> p; M6<D> P;
         for (int a = 0; a < 6; ++a) {
-          p[a] = D(p0[a]);
-          for (int c = 0; c < 6; ++c) P[a][c] = D(P0[a][c]);
+          p[a] = D(R(p0[a]), 0);
+          for (int c = 0; c < 6; ++c) P[a][c] = D(R(P0[a][c]), 0);
         }
         for (int k = 0; k < nl; ++k)
           for (int a = 0; a < 3; ++a) {
-            m[k][a] = D(m0[k][a]);
-            for (int c = 0; c < 3; ++c) V[k][a][c] = D(V0[k][a][c]);
+            m[k][a] = D(R(m0[k][a]), 0);
+            for (int c = 0; c < 3; ++c) V[k][a][c] = D(R(V0[k][a][c]), 0);
           }
         for (int c = 0; c < kGradChunk && c0 + c < nin; ++c) {
           int idx = c0 + c;
-          if (idx < 6) p[idx].d[c] = 1.0;
-          else m[(idx - 6) / 3][(idx - 6) % 3].d[c] = 1.0;
+          if (idx < 6) p[idx].d[c] = R(1.0);
+          else m[(idx - 6) / 3][(idx - 6) % 3].d[c] = R(1.0);
         }
         D chi2; uint32_t st;
         run_track<D>(geom, p, P, m.data(), V.data(), layers, nl, b, joseph != 0, chi2, st);
         for (int c = 0; c < kGradChunk && c0 + c < nin; ++c) {
           int idx = c0 + c;
-          double g = w[i] * chi2.d[c];
+          double g = w[i] * double(chi2.d[c]);
           if (idx < 6) g_par[i * 6 + idx] = g;
           else g_hit[(((idx - 6) / 3) * n + i) * 3 + (idx - 6) % 3] = g;
         }
@@ -535,8 +538,19 @@ int kfo_grad_chi2(int geom, int64_t n, int L, const double* layers, double bz, c
                   const double* hit_cov, int joseph, const double* w, double* g_hit,
                   double* g_par, int nthreads) {
   if (n < 0 || L < 0 || (geom != 0 && geom != 1)) return 1;
-  kfo::grad_batch(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, w,
-                  g_hit, g_par, nthreads);
+  kfo::grad_batch<double>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, w,
+                          g_hit, g_par, nthreads);
+  return 0;
+}
+
+// The same gradient evaluated in float arithmetic (tolerance sizing only).
+int kfo_grad_chi2_f32(int geom, int64_t n, int L, const double* layers, double bz, const int32_t* nlay,
+                      const double* par_in, const double* cov_in, const double* hit_pos,
+                      const double* hit_cov, int joseph, const double* w, double* g_hit,
+                      double* g_par, int nthreads) {
+  if (n < 0 || L < 0 || (geom != 0 && geom != 1)) return 1;
+  kfo::grad_batch<float>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, w,
+                         g_hit, g_par, nthreads);
   return 0;
 }
 

@@ -171,6 +171,54 @@ kf_status_t batched_via_graph(const kf::BatchedArgs& a, int prec, int block, int
 
 extern "C" {
 
+kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const float* hit_pos,
+                               const float* hit_cov, const float* layer_z, int32_t n_layers, int64_t n_tracks,
+                               float bz_tesla, kf_layout_t layout, const int32_t* status_fwd, const float* ckpt,
+                               const float* grad_chi2, float* grad_hit_pos, float* grad_par_in,
+                               float* grad_cov_in, const kf_tune_t* tune, void* stream) {
+  if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  int block = 256;
+  if (tune) {
+    block = tune->block_threads;
+    if (block != 64 && block != 128 && block != 256) return KF_E_FLAGS;
+  }
+  if (n_tracks == 0) return KF_OK;
+  if (!par_in || !cov_in || !status_fwd || !grad_chi2 || !grad_par_in) return KF_E_NULL;
+  if (n_layers > 0 && (!hit_pos || !hit_cov || !layer_z || !grad_hit_pos)) return KF_E_NULL;
+  const void* ptrs[] = {par_in, cov_in, hit_pos, hit_cov, status_fwd, ckpt, grad_chi2, grad_hit_pos, grad_par_in,
+                        grad_cov_in};
+  for (const void* p : ptrs)
+    if (p && !aligned4(p)) return KF_E_ALIGN;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  kf::AdjointArgs a;
+  a.par_in = par_in;
+  a.cov_in = cov_in;
+  a.hit_pos = hit_pos;
+  a.hit_cov = hit_cov;
+  a.ckpt = ckpt;
+  a.status = status_fwd;
+  a.grad_chi2 = grad_chi2;
+  a.grad_hit = grad_hit_pos;
+  a.grad_par = grad_par_in;
+  a.grad_cov = grad_cov_in;
+  a.n = n_tracks;
+  a.L = n_layers;
+  a.lay = tl;
+  a.b = float(kCLight * double(bz_tesla));
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layer_z[l] : 0.0f;
+  const hipError_t e = kf::launch_adjoint_z(block, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
+int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t layout) {
+  kf::TrackLayout tl;
+  if (n_tracks < 0 || n_layers <= 0 || !layout_ok(layout, &tl)) return 0;
+  return kf::layout_floats(n_tracks, 27, n_layers, tl);
+}
+
 int64_t kf_batched_workspace_size(int64_t n_tracks) {
   return n_tracks < 0 ? 0 : kf::batched_workspace_bytes(n_tracks);
 }

@@ -78,8 +78,24 @@ __device__ __forceinline__ float sinc_only(float u, float su) {
 }
 
 // ----------------------------------------------------------------------------
-// Propagation to a plane z = zk.  Output: propagated parameters q and the
-// transported covariance Pt = F C F^T.
+// Scalar-generic helpers: the same formulas run on float and, for the adjoint,
+// on dual numbers (kf_dual.h) to differentiate the Jacobian itself.
+__device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincos_r(x, s, c); }
+__device__ __forceinline__ float rcp_t(float x) { return rcp(x); }
+__device__ __forceinline__ void sinc_g_t(float u, float su, float cu, float& sinc, float& g) { sinc_g(u, su, cu, sinc, g); }
+
+// The non-trivial entries of the plane Jacobian F:
+//   row x   = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th
+//   row y   = e_y + b0 e_z + b1 e_k + b2 e_phi + b3 e_th
+//   row phi = c0 e_z + c1 e_k + e_phi + c3 e_th
+// rows kappa and theta are the identity's; row z is zero.
+template <class T>
+struct PlaneJac {
+  T a0, a1, a2, a3, b0, b1, b2, b3, c0, c1, c3;
+};
+
+// ----------------------------------------------------------------------------
+// Propagation to a plane z = zk.
 //
 // The transverse path to the plane is s = (zk - z) tan(theta).  With
 // u = omega s / 2 and A = phi + u the helix moves by
@@ -91,46 +107,58 @@ __device__ __forceinline__ float sinc_only(float u, float su) {
 //   d dx/d phi = -dy, d dy/d phi = dx, d phi'/d kappa = -b s,
 // dp/ds = (cos phi', sin phi', cot theta, 0, omega, 0) and
 // grad s = (0, 0, -tan theta, 0, 0, (zk - z)/cos^2 theta).  The z row of F is
-// identically zero, so the z row and column of Pt vanish.
-__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], float zk, float b,
-                                            float q[6], float Pt[21]) {
-  float sth, cth, sp, cp;
-  sincos_r(p[5], &sth, &cth);
-  sincos_r(p[4], &sp, &cp);
-  const float rcth = rcp(cth);
-  const float tanth = sth * rcth;
-  const float dz = zk - p[2];
-  const float s = dz * tanth;
-  const float om = -b * p[3];
-  const float u = 0.5f * om * s;
-  float su, cu;
-  sincos_r(u, &su, &cu);
-  float sinc, g;
-  sinc_g(u, su, cu, sinc, g);
-  const float cA = cp * cu - sp * su;
-  const float sA = sp * cu + cp * su;
-  const float chord = s * sinc;
-  const float dx = chord * cA;
-  const float dy = chord * sA;
-  const float cP = cA * cu - sA * su;  // direction at the plane
-  const float sP = sA * cu + cA * su;
+// identically zero, so the z row and column of the transported covariance vanish.
+template <class T>
+__device__ __forceinline__ void helix_to_plane(const T p[6], float zk, float b, T q[6], PlaneJac<T>& J) {
+  T sth, cth, sp, cp;
+  sincos_t(p[5], &sth, &cth);
+  sincos_t(p[4], &sp, &cp);
+  const T rcth = rcp_t(cth);
+  const T tanth = sth * rcth;
+  const T dz = zk - p[2];
+  const T s = dz * tanth;
+  const T om = -b * p[3];
+  const T u = 0.5f * om * s;
+  T su, cu;
+  sincos_t(u, &su, &cu);
+  T sinc, g;
+  sinc_g_t(u, su, cu, sinc, g);
+  const T cA = cp * cu - sp * su;
+  const T sA = sp * cu + cp * su;
+  const T chord = s * sinc;
+  const T dx = chord * cA;
+  const T dy = chord * sA;
+  const T cP = cA * cu - sA * su;  // direction at the plane
+  const T sP = sA * cu + cA * su;
   q[0] = p[0] + dx;
   q[1] = p[1] + dy;
-  q[2] = zk;
+  q[2] = T(zk);
   q[3] = p[3];
   q[4] = p[4] + om * s;
   q[5] = p[5];
 
-  const float hs2 = 0.5f * s * s;
-  const float dxdom = -hs2 * (sA * sinc + cA * g);
-  const float dydom = hs2 * (cA * sinc - sA * g);
-  const float dsdth = dz * rcth * rcth;
-  // F row x = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th, likewise row y (b*),
-  // row phi = c0 e_z + c1 e_k + e_phi + c3 e_th; rows kappa, theta = identity.
-  const float a0 = -tanth * cP, a1 = -b * dxdom, a2 = -dy, a3 = cP * dsdth;
-  const float b0 = -tanth * sP, b1 = -b * dydom, b2 = dx, b3 = sP * dsdth;
-  const float c0 = -om * tanth, c1 = -b * s, c3 = om * dsdth;
+  const T hs2 = 0.5f * s * s;
+  const T dxdom = -hs2 * (sA * sinc + cA * g);
+  const T dydom = hs2 * (cA * sinc - sA * g);
+  const T dsdth = dz * rcth * rcth;
+  J.a0 = -tanth * cP;
+  J.a1 = -b * dxdom;
+  J.a2 = -dy;
+  J.a3 = cP * dsdth;
+  J.b0 = -tanth * sP;
+  J.b1 = -b * dydom;
+  J.b2 = dx;
+  J.b3 = sP * dsdth;
+  J.c0 = -om * tanth;
+  J.c1 = -b * s;
+  J.c3 = om * dsdth;
+}
 
+// Pt = F C F^T for the plane Jacobian, on packed covariances.
+__device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const float C[21], float Pt[21]) {
+  const float a0 = J.a0, a1 = J.a1, a2 = J.a2, a3 = J.a3;
+  const float b0 = J.b0, b1 = J.b1, b2 = J.b2, b3 = J.b3;
+  const float c0 = J.c0, c1 = J.c1, c3 = J.c3;
   // W_r = C F_r^T (column r of C F^T) for the three non-trivial rows
   float Wx[6], Wy[6], Wf[6];
 #pragma unroll
@@ -161,6 +189,13 @@ __device__ __forceinline__ void propagate_z(const float p[6], const float C[21],
   Pt[ix(5, 3)] = C[ix(5, 3)];
   Pt[ix(5, 4)] = Wf[5];
   Pt[ix(5, 5)] = C[ix(5, 5)];
+}
+
+__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], float zk, float b,
+                                            float q[6], float Pt[21]) {
+  PlaneJac<float> J;
+  helix_to_plane<float>(p, zk, b, q, J);
+  transport_plane(J, C, Pt);
 }
 
 // ----------------------------------------------------------------------------

@@ -33,6 +33,26 @@ struct StepArgs {
   float layer[KF_MAX_LAYERS];
 };
 
+struct AdjointArgs {
+  const float* par_in;
+  const float* cov_in;
+  const float* hit_pos;
+  const float* hit_cov;
+  const float* ckpt;       // per-layer entering states, or NULL: recompute
+  const int32_t* status;   // the forward's status words
+  const float* grad_chi2;  // dL/dchi2_i
+  float* grad_hit;         // dL/dm, per layer
+  float* grad_par;         // dL/dp0
+  float* grad_cov;         // dL/dC0 or NULL
+  int64_t n;
+  int32_t L;
+  TrackLayout lay;
+  float b;
+  float layer[KF_MAX_LAYERS];
+};
+
+hipError_t launch_adjoint_z(int block, const AdjointArgs& a, hipStream_t s);
+
 // precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
 hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);
 

@@ -90,6 +90,11 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [vp, vp, i32, i32, i64, Layout, vp]
             fn.restype = ctypes.c_int
+        L.kf_chi2_backward_z.argtypes = [vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, vp, vp, vp, vp, vp,
+                                         ctypes.POINTER(Tune), vp]
+        L.kf_chi2_backward_z.restype = ctypes.c_int
+        L.kf_checkpoint_floats.argtypes = [i64, i32, Layout]
+        L.kf_checkpoint_floats.restype = i64
         L.kf_batched_workspace_size.argtypes = [i64]
         L.kf_batched_workspace_size.restype = i64
         L.kf_propagate_update_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, f32, Layout,
@@ -200,6 +205,7 @@ class StepLauncher:
 
     def __init__(self, geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n_tracks: int,
                  out, chi2, status, nlay=None, layout=SOA, flags: int = 0, ckpt=None, tune=None, stream=None):
+        """Arguments as propagate_update; out = (par_out, cov_out)."""
         import torch
         _require_cuda(par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, *out)
         self._layers = np.ascontiguousarray(layers, np.float32)
@@ -404,3 +410,78 @@ def run_batched(st: dict, flags: int = 0, tune=None, stream=None, workspace=None
 
 def release_graphs():
     lib().kf_batched_release()
+
+
+# ----------------------------------------------------------------------------
+# adjoint of the summed chi-square (planes)
+def checkpoint_buffer(n: int, L: int, layout, device="cuda"):
+    """Per-layer entering states for the adjoint: [L][27] per track in `layout`."""
+    return empty_like_layout(27, L, n, layout, device)
+
+
+def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None):
+    """kf_chi2_backward_z on a staged plane sample; returns (grad_hit_pos, grad_par, grad_cov or None)
+    shaped like st["hit_pos"], st["par"], st["cov"]."""
+    import torch
+    _require_cuda(status, grad_chi2, ckpt)
+    gh = torch.empty_like(st["hit_pos"])
+    gp = torch.empty_like(st["par"])
+    gc = torch.empty_like(st["cov"]) if want_cov else None
+    layers = np.ascontiguousarray(st["layers"], np.float32)
+    tn = None if tune is None else ctypes.byref(make_tune(tune))
+    with torch.cuda.device(st["par"].device):
+        rc = lib().kf_chi2_backward_z(_ptr(st["par"]), _ptr(st["cov"]), _ptr(st["hit_pos"]), _ptr(st["hit_cov"]),
+                                      layers.ctypes.data_as(ctypes.c_void_p), int(layers.shape[0]), int(st["n"]),
+                                      float(st["bz"]), Layout(*st["layout"]), _ptr(status), _ptr(ckpt),
+                                      _ptr(grad_chi2.contiguous()), _ptr(gh), _ptr(gp), _ptr(gc), tn, _stream(stream))
+    _check(rc, "kf_chi2_backward_z")
+    return gh, gp, gc
+
+
+def _make_autograd():
+    import torch
+
+    class KFChi2(torch.autograd.Function):
+        """chi2 per track of the plane filter as a differentiable function of
+        the seed parameters and the hit positions (kf_propagate_update_z
+        forward, kf_chi2_backward_z backward).
+
+        apply(par, hit_pos, cov, hit_cov, layer_z, bz, layout, nlay, checkpoint)
+        with tensors in `layout`; checkpoint=True stores the per-layer states
+        in the forward, False recomputes them in the backward.
+        """
+
+        @staticmethod
+        def forward(ctx, par, hit_pos, cov, hit_cov, layer_z, bz, layout=SOA, nlay=None, checkpoint=True):
+            n = par.shape[-1] if layout[0] == KF_SOA else None
+            if n is None:
+                raise ValueError("KFChi2 takes SoA tensors")
+            L = int(np.asarray(layer_z).shape[0])
+            ck = checkpoint_buffer(n, L, layout, par.device) if checkpoint else None
+            _, _, chi2, status = propagate_update(0, par, cov, hit_pos, hit_cov, layer_z, bz, n, nlay=nlay,
+                                                  layout=layout, ckpt=ck)
+            ctx.st = {"par": par, "cov": cov, "hit_pos": hit_pos, "hit_cov": hit_cov, "layers": layer_z,
+                      "n": n, "bz": bz, "layout": layout}
+            ctx.save_for_backward(status)
+            ctx.ckpt = ck
+            return chi2
+
+        @staticmethod
+        def backward(ctx, grad_chi2):
+            (status,) = ctx.saved_tensors
+            gh, gp, _ = chi2_backward_z(ctx.st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt)
+            return gp, gh, None, None, None, None, None, None, None
+
+    return KFChi2
+
+
+_autograd = None
+
+
+def KFChi2():
+    """The torch.autograd.Function class (built on first use, so importing this
+    module does not import torch)."""
+    global _autograd
+    if _autograd is None:
+        _autograd = _make_autograd()
+    return _autograd

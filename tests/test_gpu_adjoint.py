@@ -1,0 +1,194 @@
+"""GPU adjoint of the summed chi-square (kf_chi2_backward_z) against the FP64
+oracle's dual-number reference gradient (itself pinned by finite differences
+in test_oracle_pins), central finite differences (h = 1e-4) of the FP64
+oracle, the closed form on the last layer, finite differences of the GPU's
+own forward, and the torch.autograd.Function.
+
+Tolerance: per track, max |g_gpu - g_ref| / max |g_ref|.  The residual
+r = m - q is a ~0.01 cm difference of positions of tens of cm, so any float
+evaluation of the filter carries ~1e-4 relative error in its states into the
+gradient 2 S^-1 r at the 1e-3 level: the FP32 build of the oracle's own
+gradient shows 2.5e-3 (hits) and 5.7e-3 (seed parameters) at worst on these
+samples.  The gate is max(1e-3, twice that FP32 error on the same input)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2409_09228_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL_GRAD = 1e-3
+
+
+def _gates(s, w=None):
+    """Reference gradient, and gates sized by the FP32 build of the same gradient."""
+    rh, rp = O.grad_chi2(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"], w=w,
+                         nlay=s["nlay"])
+    fh, fp = O.grad_chi2(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"], w=w,
+                         nlay=s["nlay"], precision="f32")
+    th = max(TOL_GRAD, 2 * _rel(fh.transpose(1, 0, 2), rh.transpose(1, 0, 2)))
+    tp = max(TOL_GRAD, 2 * _rel(fp, rp))
+    return rh.transpose(1, 0, 2), rp, th, tp
+
+
+@pytest.fixture(scope="module")
+def kf():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2409_09228_amd import kf as K
+    K.lib()
+    return K
+
+
+def _fwd_bwd(kf, sample, layout=None, checkpoint=True, w=None):
+    layout = kf.SOA if layout is None else layout
+    st = kf.stage_sample(sample, layout)
+    n, L = st["n"], st["L"]
+    ck = kf.checkpoint_buffer(n, L, layout) if checkpoint else None
+    po, co, c2, ss = kf.propagate_update_z(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                                           st["bz"], n, nlay=st["nlay"], layout=layout, ckpt=ck)
+    wt = torch.ones(n, device="cuda") if w is None else torch.from_numpy(w.astype(np.float32)).cuda()
+    gh, gp, gc = kf.chi2_backward_z(st, ss, wt, ckpt=ck, want_cov=True)
+    torch.cuda.synchronize()
+    # hit gradients as [track][layer][3]
+    if layout[0] == kf.KF_SOA:
+        ghl = gh.cpu().numpy().transpose(2, 0, 1)
+    elif layout[0] == kf.KF_AOS:
+        ghl = gh.cpu().numpy().transpose(1, 0, 2)
+    else:
+        ghl = kf.unpack(gh, 3, L, n, layout).cpu().numpy().transpose(2, 0, 1)
+    gpl = kf.from_layout(gp, 6, n, layout).astype(np.float64)
+    return ghl.astype(np.float64), gpl, c2.cpu().numpy(), ss.cpu().numpy(), gc
+
+
+def _rel(got, ref):
+    """Per track: max |diff| / max |ref| over that track's gradient entries."""
+    scale = np.maximum(np.abs(ref).max(axis=tuple(range(1, ref.ndim))), 1e-30)
+    return (np.abs(got - ref).max(axis=tuple(range(1, ref.ndim))) / scale).max()
+
+
+@pytest.mark.parametrize("checkpoint", [True, False])
+def test_gradient_matches_fp64_reference(kf, checkpoint):
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(512))
+    w = np.random.default_rng(3).uniform(0.5, 2.0, 512)
+    gh, gp, _, st, _ = _fwd_bwd(kf, s, checkpoint=checkpoint, w=w)
+    rh, rp, th, tp = _gates(s, w)
+    eh = _rel(gh, rh)
+    ep = _rel(gp, rp)
+    print("hit", eh, th, "par", ep, tp)
+    assert eh <= th and ep <= tp
+
+
+def test_gradient_matches_central_differences_h1e4(kf):
+    """Central differences with h = 1e-4 of the FP64 oracle's chi2, all 66
+    inputs of 16 tracks."""
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(16))
+    gh, gp, _, _, _ = _fwd_bwd(kf, s)
+    h = 1e-4
+
+    def chi(par, hits):
+        return O.run(0, par, s["cov"], hits, s["hit_cov"], s["layer_z"], s["bz"])[2]
+
+    fp = np.zeros((16, 6))
+    for a in range(6):
+        e = np.zeros_like(s["par"]); e[:, a] = h
+        fp[:, a] = (chi(s["par"] + e, s["hit_pos"]) - chi(s["par"] - e, s["hit_pos"])) / (2 * h)
+    fh = np.zeros((16, 20, 3))
+    for k in range(20):
+        for a in range(3):
+            e = np.zeros_like(s["hit_pos"]); e[k, :, a] = h
+            fh[:, k, a] = (chi(s["par"], s["hit_pos"] + e) - chi(s["par"], s["hit_pos"] - e)) / (2 * h)
+    _, _, th, tp = _gates(s)
+    print(_rel(gh, fh), th, _rel(gp, fp), tp)
+    assert _rel(gh, fh) <= th + 1e-4 and _rel(gp, fp) <= tp + 1e-4
+
+
+def test_checkpoint_and_recompute_agree(kf):
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(2000))
+    a = _fwd_bwd(kf, s, checkpoint=True)
+    b = _fwd_bwd(kf, s, checkpoint=False)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-5, atol=1e-5 * np.abs(a[0]).max())
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-5, atol=1e-5 * np.abs(a[1]).max())
+
+
+@pytest.mark.parametrize("layout", ["aos", "aosoa64"])
+def test_layouts_agree(kf, layout):
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(1000))
+    a = _fwd_bwd(kf, s)
+    lay = kf.AOS if layout == "aos" else kf.aosoa(64)
+    b = _fwd_bwd(kf, s, layout=lay)
+    np.testing.assert_allclose(a[0], b[0], rtol=1e-6, atol=1e-6 * np.abs(a[0]).max())
+    np.testing.assert_allclose(a[1], b[1], rtol=1e-6, atol=1e-6 * np.abs(a[1]).max())
+
+
+def test_last_layer_closed_form(kf):
+    """Nothing downstream depends on the last hit: dL/dm_L = 2 w S_L^-1 r_L,
+    with S_L and r_L from the oracle's state one layer earlier."""
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(64))
+    gh, _, _, _, _ = _fwd_bwd(kf, s)
+    _, _, th, _ = _gates(s)
+    L = s["hit_pos"].shape[0]
+    po, co, _, _ = O.run(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"],
+                         nlay=np.full(64, L - 1, np.int32))
+    for i in range(64):
+        pt, F, _ = O.propagate(0, po[i], s["layer_z"][-1], s["bz"])
+        Pt = F @ O.unpack_sym(co[i]) @ F.T
+        Sm = Pt[:3, :3] + O.unpack_sym(s["hit_cov"][-1, i])
+        ref = 2 * np.linalg.solve(Sm, s["hit_pos"][-1, i] - pt[:3])
+        assert np.abs(gh[i, -1] - ref).max() <= th * np.abs(gh[i]).max()
+
+
+def test_matches_finite_differences_of_gpu_forward(kf):
+    """Central differences of the GPU's own FP32 chi2 (step 1e-3 cm on hit
+    coordinates): the backward differentiates the forward that runs, to the
+    accuracy FP32 differencing allows."""
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(256))
+    gh, gp, c2, _, _ = _fwd_bwd(kf, s)
+
+    def chi(sample):
+        st = kf.stage_sample(sample)
+        return kf.run_staged(st)[2].cpu().numpy().astype(np.float64)
+
+    for (k, a, h) in ((0, 0, 1e-3), (7, 1, 1e-3), (19, 2, 1e-3)):
+        up, dn = dict(s), dict(s)
+        up["hit_pos"] = s["hit_pos"].copy(); up["hit_pos"][k, :, a] += h
+        dn["hit_pos"] = s["hit_pos"].copy(); dn["hit_pos"][k, :, a] -= h
+        fd = (chi(up) - chi(dn)) / (2 * h)
+        g = gh[:, k, a]
+        assert np.median(np.abs(fd - g) / np.maximum(np.abs(g), 1.0)) < 2e-2
+
+
+def test_failed_track_gradient_stops_at_its_layer(kf):
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(128))
+    s["hit_pos"] = s["hit_pos"].copy()
+    s["hit_pos"][5, 3, 1] = np.nan
+    gh, gp, _, st, _ = _fwd_bwd(kf, s)
+    assert st[3] >> 16 == 5
+    assert np.all(gh[3, 5:] == 0.0)
+    one = S.subset(s, np.array([3]))
+    one["hit_pos"], one["hit_cov"], one["nlay"] = s["hit_pos"][:5, 3:4], s["hit_cov"][:5, 3:4], np.array([5], np.int32)
+    rh, rp, th, tp = _gates(one)
+    assert _rel(gh[3:4, :5], rh) <= th
+    assert _rel(gp[3:4], rp) <= tp
+
+
+def test_autograd_function(kf):
+    s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(300))
+    w = np.linspace(0.5, 1.5, 300)
+    rh, rp, th, tp = _gates(s, w)
+    st = kf.stage_sample(s)
+    par = st["par"].clone().requires_grad_(True)
+    hp = st["hit_pos"].clone().requires_grad_(True)
+    for ckpt in (True, False):
+        chi2 = kf.KFChi2().apply(par, hp, st["cov"], st["hit_cov"], st["layers"], st["bz"], kf.SOA, st["nlay"], ckpt)
+        loss = (chi2 * torch.linspace(0.5, 1.5, 300, device="cuda")).sum()
+        par.grad = None
+        hp.grad = None
+        loss.backward()
+        gp = kf.from_soa_tensor(par.grad).astype(np.float64)
+        gh = hp.grad.cpu().numpy().transpose(2, 0, 1).astype(np.float64)
+        assert _rel(gp, rp) <= tp
+        assert _rel(gh, rh) <= th
