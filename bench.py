@@ -122,7 +122,17 @@ def bench_batched(args, sample):
     from paper_2409_09228_amd import kf as K
     from paper_2409_09228_amd import synth as S
     stream = torch.cuda.current_stream()
-    layout = parse_layout(args.layout) if args.layout != "soa" else K.AOS
+    tuned = None
+    if args.autotune:
+        from paper_2409_09228_amd import tune as T
+        t0 = time.perf_counter()
+        res = T.tune_batched(sample, flags=args.flags, use_cache=False)
+        c = res["config"]
+        tuned = {"config": c, "search_s": round(time.perf_counter() - t0, 1), "candidates": len(res["tried"]),
+                 "worst_ms": round(max(t for _, t in res["tried"]), 4)}
+        args.block, args.tpt, args.sched, args.waves_mult, args.layout = (c["block"], c["tpt"], c["schedule"],
+                                                                          c["waves_mult"], c["layout"])
+    layout = parse_layout(args.layout) if args.layout != "soa" or args.autotune else K.AOS
     st = K.stage_batched(sample, layout)
     n = st["n"]
     updates = int(sample["nlay"].sum())
@@ -171,7 +181,7 @@ def bench_batched(args, sample):
                    "waves_mult": args.waves_mult, "ok_tracks": ok,
                    "per_bucket_launches": len(launches), "per_bucket_ms": round(ms_b, 4),
                    "per_bucket_updates_per_s": round(updates / (ms_b / 1e3), 1),
-                   "speedup_vs_per_bucket": round(ms_b / ms, 3)},
+                   "speedup_vs_per_bucket": round(ms_b / ms, 3), "autotune": tuned},
     }
 
 
@@ -239,6 +249,8 @@ def main(argv=None):
     ap.add_argument("--waves-mult", type=int, default=1, help="batched form: grid in units of resident blocks")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched form: search the launch shape first and time the winner")
     ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint"],
                     help="auto: batched for mixed-geometry workloads, plain otherwise")
     ap.add_argument("--cpu-tracks", type=int, default=480000)
@@ -305,23 +317,31 @@ def main(argv=None):
             step_prealloc()
         torch.cuda.synchronize()
     ok = int(((status & 0xFF) == 0).sum().item())
-    # timed region: K launches with an event after each on the launch stream
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    # timed region: K back-to-back launches between two events on the launch
+    # stream; the average launch duration is the interval over K
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step_prealloc()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    value = updates * args.steps / (ms / 1e3)
+    kernel_ms = ms_step
+    # diagnostics only (not used above): per-launch spread, events between launches
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(min(args.steps, 50) + 1)]
     ev[0].record(stream)
-    for j in range(args.steps):
+    for j in range(len(ev) - 1):
         step_prealloc()
         ev[j + 1].record(stream)
     ev[-1].synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per = [ev[j].elapsed_time(ev[j + 1]) for j in range(args.steps)]
-    ms = ev[0].elapsed_time(ev[-1])
-    ms_step = ms / args.steps
-    value = updates * args.steps / (ms / 1e3)
-    kernel_ms = sum(per) / len(per)  # average launch duration over the timed region
-    per.sort()
+    per = sorted(ev[j].elapsed_time(ev[j + 1]) for j in range(len(ev) - 1))
 
     flops = FLOPS_PER_UPDATE[geom] * updates
     bytes_ = TRACK_BYTES * n + LAYER_BYTES * updates
