@@ -28,8 +28,8 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 # Algorithmic cost of one track-layer update (counted from the method's
-# formulation, FMA = 2 flops, each sin/cos/reciprocal/sqrt = 1 flop; the
-# derivation is listed operation by operation in the design doc).
+# formulation step by step, FMA = 2 flops, each sin/cos/reciprocal/sqrt =
+# 1 flop).
 FLOPS_PER_UPDATE = {0: 391.0, 1: 890.0}
 FP32_PEAK_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz
 PROFILES = os.path.join(ROOT, "profiles")

@@ -22,6 +22,10 @@ ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}",
     "-O3",
+    # fuse a*b+c into an FMA only inside one source expression, never across
+    # statements: the rounding of every track is then fixed by the source and
+    # identical in every kernel that runs the step (plain, persistent, adjoint)
+    "-ffp-contract=on",
     "-std=c++17",
     "-fPIC",
     "-shared",

@@ -67,7 +67,7 @@ __device__ __forceinline__ void adjoint_layer_z(const float p[6], const float P[
   const PlaneJac<float> J{Jd.a0.v, Jd.a1.v, Jd.a2.v, Jd.a3.v, Jd.b0.v, Jd.b1.v,
                           Jd.b2.v, Jd.b3.v, Jd.c0.v, Jd.c1.v, Jd.c3.v};
   float Pt[21];
-  transport_plane(J, P, Pt);
+  transport_plane<false>(J, P, Pt);
   const float S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
   const float S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
   const float c00 = S11 * S22 - S21 * S21, c10 = S20 * S21 - S10 * S22, c11 = S00 * S22 - S20 * S20;
@@ -224,11 +224,13 @@ __global__ void __launch_bounds__(256) kf_adjoint_z_kernel(const AdjointArgs a) 
       ln.template ld_all<6>(ln.par, a.par_in, 0, p);
       ln.template ld_all<21>(ln.cov, a.cov_in, 0, P);
       float chi2 = 0.0f;
+      Dir d;
+      dir_init(p, d);
       for (int j = 0; j < k; ++j) {
         float m[3], V[6];
         ln.template ld_all<3>(ln.hp, a.hit_pos, j, m);
         ln.template ld_all<6>(ln.hc, a.hit_cov, j, V);
-        layer_step<0, PREC_F32>(p, P, m, V, a.layer[j], a.b, chi2);
+        layer_at<0, PREC_F32>(j, p, P, d, m, V, a.layer[j], a.b, chi2);
       }
     }
     float m[3], V[6], gm[3];

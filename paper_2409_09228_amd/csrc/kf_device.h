@@ -28,6 +28,11 @@ __host__ __device__ constexpr int ix(int i, int j) {
 // error is far below the FP32 tolerance of the step.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Marks the rare side of a per-lane branch: the empty volatile statement
+// keeps the compiler from evaluating that side unconditionally (as a select),
+// so a wave whose lanes all take the common side skips it.
+__device__ __forceinline__ void rare_path() { __asm__ volatile(""); }
+
 __device__ __forceinline__ bool fin(float x) { return __builtin_isfinite(x); }
 __device__ __forceinline__ bool fin(double x) { return __builtin_isfinite(x); }
 
@@ -71,10 +76,74 @@ __device__ __forceinline__ void sinc_g(float u, float su, float cu, float& sinc,
   g = small ? gs : (su - u * cu) * ru * ru;
 }
 
-__device__ __forceinline__ float sinc_only(float u, float su) {
-  const float u2 = u * u;
-  const float ss = 1.0f - u2 * (1.0f / 6.0f) * (1.0f - u2 * (1.0f / 20.0f) * (1.0f - u2 * (1.0f / 42.0f) * (1.0f - u2 * (1.0f / 72.0f))));
-  return fabsf(u) < 0.5f ? ss : su * rcp(u);
+// Horner forms in u^2 of the series used on |u| < 1/2 (truncation after the
+// last term shown, relative to the function's value):
+//   sinc u   = 1 - u^2/6 + u^4/120 - u^6/5040 + u^8/362880          (< 3e-11)
+//   cos u    = 1 - u^2/2 + u^4/24 - u^6/720 + u^8/40320             (< 4e-10)
+//   G(u)/u   = 1/3 - u^2/30 + u^4/840 - u^6/45360                   (< 3e-9)
+__device__ __forceinline__ float sinc_series(float u2) {
+  return __builtin_fmaf(u2, __builtin_fmaf(u2, __builtin_fmaf(u2, __builtin_fmaf(u2, 1.0f / 362880.0f, -1.0f / 5040.0f),
+                                                                1.0f / 120.0f), -1.0f / 6.0f), 1.0f);
+}
+__device__ __forceinline__ float cos_series(float u2) {
+  return __builtin_fmaf(u2, __builtin_fmaf(u2, __builtin_fmaf(u2, __builtin_fmaf(u2, 1.0f / 40320.0f, -1.0f / 720.0f),
+                                                                1.0f / 24.0f), -0.5f), 1.0f);
+}
+__device__ __forceinline__ float g_over_u_series(float u2) {
+  return __builtin_fmaf(u2, __builtin_fmaf(u2, __builtin_fmaf(u2, -1.0f / 45360.0f, 1.0f / 840.0f), -1.0f / 30.0f),
+                        1.0f / 3.0f);
+}
+
+// sin u, cos u, sinc u and (WANT_G) G(u) for the helix's half turning angle
+// u.  Each lane takes one of two branches by its own |u|, so a track's result
+// never depends on the other tracks of its wave: the series above for
+// |u| < 1/2 (the usual case: a few degrees between layers), else the reduced
+// sin/cos and the closed forms.
+template <bool WANT_G>
+__device__ __forceinline__ void helix_trig(float u, float& su, float& cu, float& sinc, float& g) {
+  if (fabsf(u) < 0.5f) {
+    const float u2 = u * u;
+    sinc = sinc_series(u2);
+    su = u * sinc;
+    cu = cos_series(u2);
+    if (WANT_G) g = u * g_over_u_series(u2);
+  } else {
+    rare_path();
+    sincos_r(u, &su, &cu);
+    const float ru = rcp(u);
+    sinc = su * ru;
+    if (WANT_G) g = (su - u * cu) * ru * ru;
+  }
+}
+
+// sin and cos of the two direction angles (phi, theta), carried from layer to
+// layer instead of being re-evaluated: propagation hands over the direction
+// at the surface, and an update that moves an angle by d rotates the pair by
+// d.  For |d| <= 1/8 the rotation uses sin d = d - d^3/6 + d^5/120 (error
+// < 1e-10) and cos d = 1 - d^2/2 + d^4/24 - d^6/720 (< 2e-12); a larger step
+// (a poor seed) re-evaluates sin and cos of the updated angle itself.  The
+// rounding of the carried pair drifts by about one ulp per layer.
+struct Dir {
+  float sp, cp, st, ct;  // sin phi, cos phi, sin theta, cos theta
+};
+
+__device__ __forceinline__ void dir_init(const float p[6], Dir& d) {
+  sincos_r(p[4], &d.sp, &d.cp);
+  sincos_r(p[5], &d.st, &d.ct);
+}
+
+__device__ __forceinline__ void rotate_by(float& s, float& c, float d, float angle) {
+  if (fabsf(d) <= 0.125f) {
+    const float d2 = d * d;
+    const float sd = __builtin_fmaf(d * d2, __builtin_fmaf(d2, 1.0f / 120.0f, -1.0f / 6.0f), d);
+    const float cd = __builtin_fmaf(d2, __builtin_fmaf(d2, __builtin_fmaf(d2, -1.0f / 720.0f, 1.0f / 24.0f), -0.5f), 1.0f);
+    const float sn = s * cd + c * sd;
+    c = c * cd - s * sd;
+    s = sn;
+  } else {
+    rare_path();
+    sincos_r(angle, &s, &c);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -83,6 +152,9 @@ __device__ __forceinline__ float sinc_only(float u, float su) {
 __device__ __forceinline__ void sincos_t(float x, float* s, float* c) { sincos_r(x, s, c); }
 __device__ __forceinline__ float rcp_t(float x) { return rcp(x); }
 __device__ __forceinline__ void sinc_g_t(float u, float su, float cu, float& sinc, float& g) { sinc_g(u, su, cu, sinc, g); }
+__device__ __forceinline__ void helix_trig_t(float u, float& su, float& cu, float& sinc, float& g) {
+  helix_trig<true>(u, su, cu, sinc, g);
+}
 
 // The non-trivial entries of the plane Jacobian F:
 //   row x   = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th
@@ -109,27 +181,23 @@ struct PlaneJac {
 // grad s = (0, 0, -tan theta, 0, 0, (zk - z)/cos^2 theta).  The z row of F is
 // identically zero, so the z row and column of the transported covariance vanish.
 template <class T>
-__device__ __forceinline__ void helix_to_plane(const T p[6], float zk, float b, T q[6], PlaneJac<T>& J) {
-  T sth, cth, sp, cp;
-  sincos_t(p[5], &sth, &cth);
-  sincos_t(p[4], &sp, &cp);
+__device__ __forceinline__ void helix_to_plane_dir(const T p[6], const T& sth, const T& cth, const T& sp, const T& cp,
+                                                   float zk, float b, T q[6], PlaneJac<T>& J, T& sP, T& cP) {
   const T rcth = rcp_t(cth);
   const T tanth = sth * rcth;
   const T dz = zk - p[2];
   const T s = dz * tanth;
   const T om = -b * p[3];
   const T u = 0.5f * om * s;
-  T su, cu;
-  sincos_t(u, &su, &cu);
-  T sinc, g;
-  sinc_g_t(u, su, cu, sinc, g);
+  T su, cu, sinc, g;
+  helix_trig_t(u, su, cu, sinc, g);
   const T cA = cp * cu - sp * su;
   const T sA = sp * cu + cp * su;
   const T chord = s * sinc;
   const T dx = chord * cA;
   const T dy = chord * sA;
-  const T cP = cA * cu - sA * su;  // direction at the plane
-  const T sP = sA * cu + cA * su;
+  cP = cA * cu - sA * su;  // direction at the plane
+  sP = sA * cu + cA * su;
   q[0] = p[0] + dx;
   q[1] = p[1] + dy;
   q[2] = T(zk);
@@ -154,7 +222,19 @@ __device__ __forceinline__ void helix_to_plane(const T p[6], float zk, float b, 
   J.c3 = om * dsdth;
 }
 
-// Pt = F C F^T for the plane Jacobian, on packed covariances.
+// The same, evaluating the direction's sin and cos from p itself.
+template <class T>
+__device__ __forceinline__ void helix_to_plane(const T p[6], float zk, float b, T q[6], PlaneJac<T>& J) {
+  T sth, cth, sp, cp, sP, cP;
+  sincos_t(p[5], &sth, &cth);
+  sincos_t(p[4], &sp, &cp);
+  helix_to_plane_dir<T>(p, sth, cth, sp, cp, zk, b, q, J, sP, cP);
+}
+
+// Pt = F C F^T for the plane Jacobian, on packed covariances.  ZIN: the z row
+// and column of C are known to be zero (C is the result of a plane update),
+// which removes the z column from every product.
+template <bool ZIN>
 __device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const float C[21], float Pt[21]) {
   const float a0 = J.a0, a1 = J.a1, a2 = J.a2, a3 = J.a3;
   const float b0 = J.b0, b1 = J.b1, b2 = J.b2, b3 = J.b3;
@@ -163,14 +243,39 @@ __device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const 
   float Wx[6], Wy[6], Wf[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float c2 = C[ix(i, 2)], c3_ = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
-    Wx[i] = C[ix(i, 0)] + a0 * c2 + a1 * c3_ + a2 * c4 + a3 * c5;
-    Wy[i] = C[ix(i, 1)] + b0 * c2 + b1 * c3_ + b2 * c4 + b3 * c5;
-    Wf[i] = c0 * c2 + c1 * c3_ + c4 + c3 * c5;
+    const float c3_ = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
+    if (ZIN) {
+      if (i == 2) {
+        Wx[i] = Wy[i] = Wf[i] = 0.0f;
+        continue;
+      }
+      Wx[i] = C[ix(i, 0)] + a1 * c3_ + a2 * c4 + a3 * c5;
+      Wy[i] = C[ix(i, 1)] + b1 * c3_ + b2 * c4 + b3 * c5;
+      Wf[i] = c1 * c3_ + c4 + c3 * c5;
+    } else {
+      const float c2 = C[ix(i, 2)];
+      Wx[i] = C[ix(i, 0)] + a0 * c2 + a1 * c3_ + a2 * c4 + a3 * c5;
+      Wy[i] = C[ix(i, 1)] + b0 * c2 + b1 * c3_ + b2 * c4 + b3 * c5;
+      Wf[i] = c0 * c2 + c1 * c3_ + c4 + c3 * c5;
+    }
   }
-  Pt[ix(0, 0)] = Wx[0] + a0 * Wx[2] + a1 * Wx[3] + a2 * Wx[4] + a3 * Wx[5];
-  Pt[ix(1, 0)] = Wx[1] + b0 * Wx[2] + b1 * Wx[3] + b2 * Wx[4] + b3 * Wx[5];
-  Pt[ix(1, 1)] = Wy[1] + b0 * Wy[2] + b1 * Wy[3] + b2 * Wy[4] + b3 * Wy[5];
+  if (ZIN) {
+    Pt[ix(0, 0)] = Wx[0] + a1 * Wx[3] + a2 * Wx[4] + a3 * Wx[5];
+    Pt[ix(1, 0)] = Wx[1] + b1 * Wx[3] + b2 * Wx[4] + b3 * Wx[5];
+    Pt[ix(1, 1)] = Wy[1] + b1 * Wy[3] + b2 * Wy[4] + b3 * Wy[5];
+    Pt[ix(4, 0)] = c1 * Wx[3] + Wx[4] + c3 * Wx[5];
+    Pt[ix(4, 1)] = c1 * Wy[3] + Wy[4] + c3 * Wy[5];
+    Pt[ix(4, 3)] = c1 * C[ix(3, 3)] + C[ix(4, 3)] + c3 * C[ix(5, 3)];
+    Pt[ix(4, 4)] = c1 * Wf[3] + Wf[4] + c3 * Wf[5];
+  } else {
+    Pt[ix(0, 0)] = Wx[0] + a0 * Wx[2] + a1 * Wx[3] + a2 * Wx[4] + a3 * Wx[5];
+    Pt[ix(1, 0)] = Wx[1] + b0 * Wx[2] + b1 * Wx[3] + b2 * Wx[4] + b3 * Wx[5];
+    Pt[ix(1, 1)] = Wy[1] + b0 * Wy[2] + b1 * Wy[3] + b2 * Wy[4] + b3 * Wy[5];
+    Pt[ix(4, 0)] = c0 * Wx[2] + c1 * Wx[3] + Wx[4] + c3 * Wx[5];
+    Pt[ix(4, 1)] = c0 * Wy[2] + c1 * Wy[3] + Wy[4] + c3 * Wy[5];
+    Pt[ix(4, 3)] = c0 * C[ix(2, 3)] + c1 * C[ix(3, 3)] + C[ix(4, 3)] + c3 * C[ix(5, 3)];
+    Pt[ix(4, 4)] = c0 * Wf[2] + c1 * Wf[3] + Wf[4] + c3 * Wf[5];
+  }
   Pt[ix(2, 0)] = 0.0f;
   Pt[ix(2, 1)] = 0.0f;
   Pt[ix(2, 2)] = 0.0f;
@@ -178,11 +283,7 @@ __device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const 
   Pt[ix(3, 1)] = Wy[3];
   Pt[ix(3, 2)] = 0.0f;
   Pt[ix(3, 3)] = C[ix(3, 3)];
-  Pt[ix(4, 0)] = c0 * Wx[2] + c1 * Wx[3] + Wx[4] + c3 * Wx[5];
-  Pt[ix(4, 1)] = c0 * Wy[2] + c1 * Wy[3] + Wy[4] + c3 * Wy[5];
   Pt[ix(4, 2)] = 0.0f;
-  Pt[ix(4, 3)] = c0 * C[ix(2, 3)] + c1 * C[ix(3, 3)] + C[ix(4, 3)] + c3 * C[ix(5, 3)];
-  Pt[ix(4, 4)] = c0 * Wf[2] + c1 * Wf[3] + Wf[4] + c3 * Wf[5];
   Pt[ix(5, 0)] = Wx[5];
   Pt[ix(5, 1)] = Wy[5];
   Pt[ix(5, 2)] = 0.0f;
@@ -191,11 +292,13 @@ __device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const 
   Pt[ix(5, 5)] = C[ix(5, 5)];
 }
 
-__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], float zk, float b,
+// d: sin and cos of the direction angles of p on entry, of q on return.
+template <bool ZIN>
+__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], Dir& d, float zk, float b,
                                             float q[6], float Pt[21]) {
   PlaneJac<float> J;
-  helix_to_plane<float>(p, zk, b, q, J);
-  transport_plane(J, C, Pt);
+  helix_to_plane_dir<float>(p, d.st, d.ct, d.sp, d.cp, zk, b, q, J, d.sp, d.cp);
+  transport_plane<ZIN>(J, C, Pt);
 }
 
 // ----------------------------------------------------------------------------
@@ -210,13 +313,12 @@ __device__ __forceinline__ void propagate_z(const float p[6], const float C[21],
 // The Jacobian adds to the fixed-s partials the path-length term with
 // grad s = -(x J_s[x,:] + y J_s[y,:]) / (x cos phi' + y sin phi'),
 // which keeps the propagated point on the cylinder to first order.
-// Branch-free; returns status bits (0 on success): an unreachable cylinder
-// first, then a crossing the iteration did not land on.
-__device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[21], float rk, float b,
+// Returns status bits (0 on success): an unreachable cylinder first, then a
+// crossing the iteration did not land on.  d: sin and cos of the direction
+// angles of p on entry, of q on return.
+__device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[21], Dir& d, float rk, float b,
                                                 float q[6], float Pt[21]) {
-  float sth, cth, sp, cp;
-  sincos_r(p[5], &sth, &cth);
-  sincos_r(p[4], &sp, &cp);
+  const float sth = d.st, cth = d.ct, sp = d.sp, cp = d.cp;
   const float om = -b * p[3];
   const float x = p[0], y = p[1];
   const float rho2 = x * x + y * y;
@@ -228,9 +330,8 @@ __device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[
 #pragma unroll
   for (int it = 0; it < 5; ++it) {
     const float u = 0.5f * om * s;
-    float su, cu;
-    sincos_r(u, &su, &cu);
-    const float sinc = sinc_only(u, su);
+    float su, cu, sinc, unused;
+    helix_trig<false>(u, su, cu, sinc, unused);
     const float cA = cp * cu - sp * su;
     const float sA = sp * cu + cp * su;
     const float ch = s * sinc;
@@ -243,10 +344,8 @@ __device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[
     s = s - gg * rcp(gp);
   }
   const float u = 0.5f * om * s;
-  float su, cu;
-  sincos_r(u, &su, &cu);
-  float sinc, g;
-  sinc_g(u, su, cu, sinc, g);
+  float su, cu, sinc, g;
+  helix_trig<true>(u, su, cu, sinc, g);
   const float cA = cp * cu - sp * su;
   const float sA = sp * cu + cp * su;
   const float ch = s * sinc;
@@ -254,6 +353,8 @@ __device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[
   const float X = x + dx, Y = y + dy;
   const float cP = cA * cu - sA * su;
   const float sP = sA * cu + cA * su;
+  d.cp = cP;
+  d.sp = sP;
   const bool on_surface = fabsf(X * X + Y * Y - rk2) <= 2.0e-4f * rk2;
   const float rsth = rcp(sth);
   const float cot = cth * rsth;
@@ -476,14 +577,15 @@ __device__ __forceinline__ uint32_t update(float q[6], float Pt[21], const float
   return update_f64<true>(q, Pt, m, V, dchi);
 }
 
-template <int GEOM>
-__device__ __forceinline__ uint32_t propagate(const float p[6], const float C[21], float target, float b,
+// ZIN (planes): C has the zero z row and column a plane update leaves.
+template <int GEOM, bool ZIN>
+__device__ __forceinline__ uint32_t propagate(const float p[6], const float C[21], Dir& d, float target, float b,
                                               float q[6], float Pt[21]) {
   if (GEOM == 0) {
-    propagate_z(p, C, target, b, q, Pt);
+    propagate_z<ZIN>(p, C, d, target, b, q, Pt);
     return 0u;
   }
-  return propagate_r(p, C, target, b, q, Pt);
+  return propagate_r(p, C, d, target, b, q, Pt);
 }
 
 }  // namespace kf

@@ -92,4 +92,9 @@ __device__ __forceinline__ void sinc_g_t(const D4& u, const D4& su, const D4& cu
   g = chain(u, g0, dg);
 }
 
+__device__ __forceinline__ void helix_trig_t(const D4& u, D4& su, D4& cu, D4& sinc, D4& g) {
+  sincos_t(u, &su, &cu);
+  sinc_g_t(u, su, cu, sinc, g);
+}
+
 }  // namespace kf

@@ -5,10 +5,13 @@
 //   SoA:      lane_offset = i,                      layer_stride = E*n,  es = n
 //   AoSoA-B:  lane_offset = (i/B)*(E*L*B) + i%B,    layer_stride = E*B,  es = B
 //   AoS:      lane_offset = i*E,                    layer_stride = n*E,  es = 1
-// Only the first term differs between the lanes of a wave, so every load is a
-// wave-uniform base plus a per-lane byte offset computed once per track: no
-// per-element address arithmetic in the layer loop beyond one add.  Byte
-// offsets are 32-bit unless an array spans 4 GiB or more (WIDE).
+// Only the first term differs between the lanes of a wave, so every access is
+// a wave-uniform byte offset plus a per-lane byte offset computed once per
+// track.  Arrays below 4 GiB are accessed through buffer resources (base and
+// size in scalar registers): the per-lane offset is one 32-bit VGPR, the
+// uniform offset a scalar register, and no 64-bit address is formed per
+// element; accesses past the array's end read zero and write nothing.  Larger
+// arrays (WIDE) use 64-bit global addresses.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,7 +31,7 @@ __host__ __device__ inline int64_t layout_offset(int64_t i, int64_t n, int E, in
 }
 
 // Floats spanned by one array of E elements per track and L layers.
-inline int64_t layout_floats(int64_t n, int E, int L, TrackLayout lay) {
+__host__ __device__ inline int64_t layout_floats(int64_t n, int E, int L, TrackLayout lay) {
   if (lay.kind == KF_AOSOA) {
     const int64_t B = int64_t(1) << lay.shift;
     return ((n + B - 1) / B) * B * E * (L > 0 ? L : 1);
@@ -62,16 +65,78 @@ __device__ __forceinline__ void st_rec(float* p, const float* src) {
   __builtin_memcpy(p, &r, sizeof(r));
 }
 
+// Buffer-resource word 3 for untyped 32-bit access on gfx9-family parts.
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, int(bytes), kBufWord3);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), 0);
+}
+// Element j of a vector of dwords as a float.  The element is copied to a
+// scalar first: a bit cast applied directly to a vector subscript reads
+// element 0 with this compiler.
+template <class V>
+__device__ __forceinline__ float lane_word(const V& v, int j) {
+  const unsigned w = v[j];
+  return __builtin_bit_cast(float, w);
+}
+// N consecutive floats of one lane: dwordx4 pieces, then x3/x2/x1 for the rest
+template <int N>
+__device__ __forceinline__ void buf_ld_rec(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float* dst) {
+#pragma unroll
+  for (int c = 0; c + 4 <= N; c += 4) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff + 4 * c), 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dst[c + j] = lane_word(v, j);
+  }
+  constexpr int c = N & ~3;
+  if (N - c == 3) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff + 4 * c), 0);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dst[c + j] = lane_word(v, j);
+  } else if (N - c == 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff + 4 * c), 0);
+    dst[c] = lane_word(v, 0);
+    dst[c + 1] = lane_word(v, 1);
+  } else if (N - c == 1) {
+    dst[c] = buf_ld(r, voff, soff + 4 * c);
+  }
+}
+template <int N>
+__device__ __forceinline__ void buf_st_rec(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, const float* src) {
+#pragma unroll
+  for (int c = 0; c + 4 <= N; c += 4) {
+    __attribute__((ext_vector_type(4))) unsigned v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = __builtin_bit_cast(unsigned, src[c + j]);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, int(voff), int(soff + 4 * c), 0);
+  }
+  constexpr int c = N & ~3;
+  if (N - c == 3) {
+    __attribute__((ext_vector_type(3))) unsigned v;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = __builtin_bit_cast(unsigned, src[c + j]);
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, int(voff), int(soff + 4 * c), 0);
+  } else if (N - c == 2) {
+    __attribute__((ext_vector_type(2))) unsigned v;
+    v[0] = __builtin_bit_cast(unsigned, src[c]);
+    v[1] = __builtin_bit_cast(unsigned, src[c + 1]);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), int(soff + 4 * c), 0);
+  } else if (N - c == 1) {
+    buf_st(r, voff, soff + 4 * c, src[c]);
+  }
+}
+
 template <bool WIDE>
 struct LaneRef {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
-  Off boff;  // byte offset of this lane's element 0, layer 0
-  __device__ __forceinline__ float ld(const float* base, int64_t uni) const {
-    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base + uni) + boff);
-  }
-  __device__ __forceinline__ void st(float* base, int64_t uni, float v) const {
-    *reinterpret_cast<float*>(reinterpret_cast<char*>(base + uni) + boff) = v;
-  }
+  Off boff;        // byte offset of this lane's element 0, layer 0
+  uint32_t bytes;  // size of the array (buffer form)
   __device__ __forceinline__ const float* at(const float* base, int64_t uni) const {
     return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base + uni) + boff);
   }
@@ -106,27 +171,50 @@ struct Lanes {
       es = n;
       par.boff = cov.boff = hp.boff = hc.boff = ck.boff = Off(i * 4);
     }
+    if (!WIDE) {
+      par.bytes = uint32_t(layout_floats(n, 6, 1, lay) * 4);
+      cov.bytes = uint32_t(layout_floats(n, 21, 1, lay) * 4);
+      hp.bytes = uint32_t(layout_floats(n, 3, L, lay) * 4);
+      hc.bytes = uint32_t(layout_floats(n, 6, L, lay) * 4);
+      ck.bytes = uint32_t(layout_floats(n, 27, L, lay) * 4);
+    }
   }
   // E consecutive elements of one layer (AoS records) from / to array `base`
   template <int E>
   __device__ __forceinline__ void ld_all(const LaneRef<WIDE>& r, const float* base, int l, float* dst) const {
-    if (KIND == KF_AOS) {
+    if constexpr (!WIDE) {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
+      if (KIND == KF_AOS) {
+        buf_ld_rec<E>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) dst[e] = buf_ld(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
+      }
+    } else if (KIND == KF_AOS) {
       ld_rec<E>(r.at(base, uni(E, l, 0)), dst);
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) dst[e] = r.ld(base, uni(E, l, e));
+      for (int e = 0; e < E; ++e) dst[e] = *r.at(base, uni(E, l, e));
     }
   }
   template <int E>
   __device__ __forceinline__ void st_all(const LaneRef<WIDE>& r, float* base, int l, const float* src) const {
-    if (KIND == KF_AOS) {
+    if constexpr (!WIDE) {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
+      if (KIND == KF_AOS) {
+        buf_st_rec<E>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) buf_st(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u, src[e]);
+      }
+    } else if (KIND == KF_AOS) {
       st_rec<E>(r.at(base, uni(E, l, 0)), src);
     } else {
 #pragma unroll
-      for (int e = 0; e < E; ++e) r.st(base, uni(E, l, e), src[e]);
+      for (int e = 0; e < E; ++e) *r.at(base, uni(E, l, e)) = src[e];
     }
   }
-  // wave-uniform part of the offset of element e (of E) on layer l
+  // wave-uniform part of the offset of element e (of E) on layer l, in floats
   __device__ __forceinline__ int64_t uni(int E, int l, int e) const {
     const int64_t lstride = KIND == KF_AOS ? n * E : int64_t(E) * es;
     return int64_t(l) * lstride + int64_t(e) * es;

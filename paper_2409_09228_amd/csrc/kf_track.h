@@ -13,15 +13,20 @@
 namespace kf {
 
 // One layer: propagate to surface `target`, transport the covariance, update
-// with hit (m, V).  On success the state (p, C) and chi2 advance in place and 0
-// is returned; otherwise the status bits, with (p, C) left undefined.
-template <int GEOM, int PREC>
-__device__ __forceinline__ uint32_t layer_step(float p[6], float C[21], const float m[3], const float V[6],
+// with hit (m, V).  On success the state (p, C), the sin/cos of its direction
+// angles d, and chi2 advance in place and 0 is returned; otherwise the status
+// bits, with (p, C, d) left undefined.  ZIN: C carries the zero z row and
+// column of a preceding plane update.
+template <int GEOM, int PREC, bool ZIN>
+__device__ __forceinline__ uint32_t layer_step(float p[6], float C[21], Dir& d, const float m[3], const float V[6],
                                                float target, float b, float& chi2) {
   float q[6], Pt[21];
-  const uint32_t fp = propagate<GEOM>(p, C, target, b, q, Pt);
+  const uint32_t fp = propagate<GEOM, ZIN>(p, C, d, target, b, q, Pt);
+  const float phi = q[4], theta = q[5];
   float dchi;
   const uint32_t fu = update<GEOM, PREC>(q, Pt, m, V, dchi);
+  rotate_by(d.sp, d.cp, q[4] - phi, q[4]);
+  rotate_by(d.st, d.ct, q[5] - theta, q[5]);
 #pragma unroll
   for (int e = 0; e < 6; ++e) p[e] = q[e];
 #pragma unroll
@@ -39,6 +44,15 @@ struct NoCkpt {
   __device__ __forceinline__ void operator()(int, const float*, const float*) const {}
 };
 
+// Layer k of a track: from the second layer on, a plane step knows the zero
+// z row and column its predecessor left in C.
+template <int GEOM, int PREC>
+__device__ __forceinline__ uint32_t layer_at(int k, float p[6], float C[21], Dir& d, const float m[3],
+                                             const float V[6], float target, float b, float& chi2) {
+  if (GEOM == 0 && k > 0) return layer_step<GEOM, PREC, true>(p, C, d, m, V, target, b, chi2);
+  return layer_step<GEOM, PREC, false>(p, C, d, m, V, target, b, chi2);
+}
+
 template <int GEOM, int PREC, class State, class Hits, class Ckpt>
 __device__ __forceinline__ void run_track(const State& state, const Hits& hits, const Ckpt& ckpt, int nl,
                                           const float* layer, float b, float& chi2_out, uint32_t& status_out) {
@@ -47,21 +61,28 @@ __device__ __forceinline__ void run_track(const State& state, const Hits& hits, 
   float chi2 = 0.0f;
   int k = 0;
   if (!flags && nl > 0) {
-    // hits of the next layer are fetched one layer ahead
-    float mn[3], Vn[6];
-    hits.load(0, mn, Vn);
-    for (; k < nl; ++k) {
-      float m[3], V[6];
+    Dir d;
+    dir_init(p, d);
+    // hits of the next layer are fetched one layer ahead; the first layer is
+    // peeled so that the loop body is the plane step that knows C's zero z row
+    float m[3], V[6], mn[3], Vn[6];
+    hits.load(0, m, V);
+    hits.load(hits.next(0, nl), mn, Vn);
+    ckpt(0, p, C);
+    flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
+    if (!flags) {
+      for (k = 1; k < nl; ++k) {
 #pragma unroll
-      for (int e = 0; e < 3; ++e) m[e] = mn[e];
+        for (int e = 0; e < 3; ++e) m[e] = mn[e];
 #pragma unroll
-      for (int e = 0; e < 6; ++e) V[e] = Vn[e];
-      hits.load(hits.next(k, nl), mn, Vn);
-      ckpt(k, p, C);
-      const uint32_t f = layer_step<GEOM, PREC>(p, C, m, V, layer[k], b, chi2);
-      if (f) {
-        flags = f;
-        break;
+        for (int e = 0; e < 6; ++e) V[e] = Vn[e];
+        hits.load(hits.next(k, nl), mn, Vn);
+        ckpt(k, p, C);
+        const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+        if (f) {
+          flags = f;
+          break;
+        }
       }
     }
   }
@@ -70,10 +91,12 @@ __device__ __forceinline__ void run_track(const State& state, const Hits& hits, 
     // recompute the state from before the failing layer
     state.load(p, C);
     chi2 = 0.0f;
+    Dir d;
+    dir_init(p, d);
     for (int j = 0; j < done; ++j) {
       float m[3], V[6];
       hits.load(j, m, V);
-      layer_step<GEOM, PREC>(p, C, m, V, layer[j], b, chi2);
+      layer_at<GEOM, PREC>(j, p, C, d, m, V, layer[j], b, chi2);
     }
   }
   state.store(p, C);

@@ -34,10 +34,18 @@ def _oracle(sample, joseph=False):
     return O.run_sample(sample, joseph=joseph)
 
 
-@pytest.mark.parametrize("layout", [None, ("aos", 16), ("aos", 32), ("aos", 64), ("aos", 128), ("aos", 256)])
+def _layout(kf, name):
+    if name == "soa":
+        return kf.SOA
+    if name == "aos":
+        return kf.AOS
+    return kf.aosoa(int(name[5:]))
+
+
+@pytest.mark.parametrize("layout", ["soa", "aos", "aosoa16", "aosoa32", "aosoa64", "aosoa128", "aosoa256"])
 def test_p2z_8192_all_layouts(kf, layout):
     s = S.generate("p2z_1x8192")
-    lay = None if layout is None else kf.aosoa(layout[1])
+    lay = _layout(kf, layout)
     got = _gpu_run(kf, s, lay)
     m = metrics(_oracle(s), got, 0)
     print(layout, m)
@@ -45,9 +53,10 @@ def test_p2z_8192_all_layouts(kf, layout):
     assert np.all(got[3] == 20 << 16)
 
 
-def test_p2r_9600(kf):
+@pytest.mark.parametrize("layout", ["soa", "aos", "aosoa64"])
+def test_p2r_9600(kf, layout):
     s = S.generate("p2r_100x9600", n_events=1)
-    got = _gpu_run(kf, s)
+    got = _gpu_run(kf, s, _layout(kf, layout))
     ref = _oracle(s)
     m = metrics(ref, got, 1)
     print(m)
