@@ -138,20 +138,25 @@ struct RaggedHits {
     ld_rec<3>(hp + 3 * k, m);
     ld_rec<6>(hc + 6 * k, V);
   }
-  __device__ __forceinline__ int next(int k, int nl) const { return k + 1 < nl ? k + 1 : k; }
+  int last;  // the track's last layer (its work item's layer count - 1, wave-uniform)
+  // rows of different tracks are scattered: multi-dword record loads into
+  // registers, one layer ahead
+  static constexpr bool kStaged = false;
+  __device__ __forceinline__ int next(int k) const { return k < last ? k + 1 : k; }
+  __device__ __forceinline__ void stage(int, float*) const {}
 };
 
 template <int PREC, int KIND, bool WIDE>
-__device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geom, int nl) {
+__device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geom, int nl, float* ring) {
   const Lanes<KIND, WIDE> ln(t, a.n, 1, a.lay);
   const int64_t h0 = a.hit_offset[t];
-  const RaggedHits hits{a.hit_pos + h0 * 3, a.hit_cov + h0 * 6};
+  const RaggedHits hits{a.hit_pos + h0 * 3, a.hit_cov + h0 * 6, nl > 0 ? nl - 1 : 0};
   float chi2;
   uint32_t status;
   if (geom == 0)
-    run_track<0, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_z, a.b, chi2, status);
+    run_track<0, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_z, a.b, ring, chi2, status);
   else
-    run_track<1, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_r, a.b, chi2, status);
+    run_track<1, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_r, a.b, ring, chi2, status);
   if (a.chi2) a.chi2[t] = chi2;
   if (a.status) a.status[t] = int32_t(status);
 }
@@ -164,6 +169,7 @@ __device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geo
 //                     (no atomics; the items are already longest-first)
 template <int PREC, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
+  float* ring = nullptr;  // ragged hits are not staged through LDS
   const int lane = threadIdx.x & 63;
   const int W = 64 * a.tpt;
   const int n_waves = int(gridDim.x * (blockDim.x >> 6));
@@ -177,7 +183,7 @@ __global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
     const int64_t end = int64_t(a.ws.bucket_base[b]) + a.ws.bucket_count[b];  // first slot past the bucket
     for (int u = 0; u < a.tpt; ++u) {
       const int64_t slot = slot0 + u * 64 + lane;
-      if (slot < end) run_one<PREC, KIND, WIDE>(a, a.ws.perm[slot], geom, nl);
+      if (slot < end) run_one<PREC, KIND, WIDE>(a, a.ws.perm[slot], geom, nl, ring);
     }
     if (a.schedule == KF_SCHED_STATIC) {
       item += n_waves;
@@ -196,12 +202,13 @@ static hipError_t launch_run(const BatchedArgs& a, int block, hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
     return hipErrorInvalidDevice;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf_batched_kernel<PREC, KIND, WIDE>, block, 0) !=
+  const size_t lds = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf_batched_kernel<PREC, KIND, WIDE>, block, lds) !=
           hipSuccess ||
       per_cu <= 0)
     per_cu = 1;
   const int mult = a.waves_mult > 0 ? a.waves_mult : 1;
-  hipLaunchKernelGGL((kf_batched_kernel<PREC, KIND, WIDE>), dim3(unsigned(per_cu * n_cu * mult)), dim3(block), 0, s,
+  hipLaunchKernelGGL((kf_batched_kernel<PREC, KIND, WIDE>), dim3(unsigned(per_cu * n_cu * mult)), dim3(block), lds, s,
                      a);
   return hipGetLastError();
 }

@@ -65,6 +65,9 @@ __device__ __forceinline__ void st_rec(float* p, const float* src) {
   __builtin_memcpy(p, &r, sizeof(r));
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void gbl_void;
+
 // Buffer-resource word 3 for untyped 32-bit access on gfx9-family parts.
 constexpr int kBufWord3 = 0x00020000;
 
@@ -213,6 +216,39 @@ struct Lanes {
 #pragma unroll
       for (int e = 0; e < E; ++e) *r.at(base, uni(E, l, e)) = src[e];
     }
+  }
+  // Asynchronous copy of the E elements of one layer straight into LDS:
+  // element e of lane j lands at lds[e * 64 + j] (lds wave-uniform).  The
+  // layer is min(j_uni, the lane's last layer): j_uni is wave-uniform and
+  // <= L - 1, last_off the lane's byte offset of its last layer (layer_off).
+  // Completion is tracked by the wave's vector-memory counter only; the
+  // caller waits before reading.
+  template <int E>
+  __device__ __forceinline__ void stage(const LaneRef<WIDE>& r, const float* base, int j_uni,
+                                        typename LaneRef<WIDE>::Off last_off, float* lds) const {
+    using Off = typename LaneRef<WIDE>::Off;
+    const int64_t lstride = KIND == KF_AOS ? n * E : int64_t(E) * es;  // floats per layer
+    Off off = r.boff + Off(j_uni) * Off(lstride * 4);
+    off = off < last_off ? off : last_off;
+    if constexpr (!WIDE) {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + e * 64), 4, int(off), int(uint32_t(e * es * 4)),
+                                                 0, 0);
+    } else {
+      const float* p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        __builtin_amdgcn_global_load_lds((gbl_void*)(p + e * es), (lds_void*)(lds + e * 64), 4, 0, 0);
+    }
+  }
+  // byte offset of this lane's layer l (element 0) in a per-layer array of E elements
+  template <int E>
+  __device__ __forceinline__ typename LaneRef<WIDE>::Off layer_off(const LaneRef<WIDE>& r, int l) const {
+    using Off = typename LaneRef<WIDE>::Off;
+    const int64_t lstride = KIND == KF_AOS ? n * E : int64_t(E) * es;
+    return r.boff + Off(l) * Off(lstride * 4);
   }
   // wave-uniform part of the offset of element e (of E) on layer l, in floats
   __device__ __forceinline__ int64_t uni(int E, int l, int e) const {

@@ -29,14 +29,29 @@ struct LaidOutState {
 
 template <int KIND, bool WIDE>
 struct LaidOutHits {
+  using Off = typename LaneRef<WIDE>::Off;
   const StepArgs& a;
   const Lanes<KIND, WIDE>& ln;
+  Off hp_last, hc_last;  // this lane's offsets of its last layer
+  __device__ __forceinline__ LaidOutHits(const StepArgs& a_, const Lanes<KIND, WIDE>& ln_, int nl)
+      : a(a_), ln(ln_) {
+    const int last = nl > 0 ? nl - 1 : 0;
+    hp_last = ln.template layer_off<3>(ln.hp, last);
+    hc_last = ln.template layer_off<6>(ln.hc, last);
+  }
   __device__ __forceinline__ void load(int k, float m[3], float V[6]) const {
     ln.template ld_all<3>(ln.hp, a.hit_pos, k, m);
     ln.template ld_all<6>(ln.hc, a.hit_cov, k, V);
   }
-  // wave-uniform prefetch index, always inside the hit arrays
-  __device__ __forceinline__ int next(int k, int) const { return k + 1 < a.L ? k + 1 : k; }
+  // AoS records are fetched into registers; element-major layouts through LDS
+  static constexpr bool kStaged = KIND != KF_AOS;
+  __device__ __forceinline__ int next(int k) const { return k + 1 < a.L ? k + 1 : k; }
+  // layer min(j, the track's last layer); j is wave-uniform
+  __device__ __forceinline__ void stage(int j, float* slot) const {
+    const int ju = j < a.L - 1 ? j : a.L - 1;
+    ln.template stage<3>(ln.hp, a.hit_pos, ju, hp_last, slot);
+    ln.template stage<6>(ln.hc, a.hit_cov, ju, hc_last, slot + 3 * 64);
+  }
 };
 
 template <int KIND, bool WIDE>
@@ -54,8 +69,11 @@ struct LaidOutCkpt {
   }
 };
 
+// dynamic LDS: kRingFloats per wave of the block (layouts whose hits are staged)
 template <int GEOM, int PREC, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_step_kernel(const StepArgs a) {
+  extern __shared__ float kf_lds[];
+  float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kRingFloats;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
@@ -63,8 +81,8 @@ __global__ void __launch_bounds__(256) kf_step_kernel(const StepArgs a) {
   nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
   float chi2;
   uint32_t status;
-  run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, LaidOutHits<KIND, WIDE>{a, ln},
-                        LaidOutCkpt<KIND, WIDE>{a, ln}, nl, a.layer, a.b, chi2, status);
+  run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, LaidOutHits<KIND, WIDE>(a, ln, nl),
+                        LaidOutCkpt<KIND, WIDE>{a, ln}, nl, a.layer, a.b, ring, chi2, status);
   if (a.chi2) a.chi2[i] = chi2;
   if (a.status) a.status[i] = int32_t(status);
 }
@@ -72,7 +90,8 @@ __global__ void __launch_bounds__(256) kf_step_kernel(const StepArgs a) {
 template <int GEOM, int PREC, int KIND, bool WIDE>
 static hipError_t launch_one(int block, const StepArgs& a, hipStream_t s) {
   const int64_t grid = (a.n + block - 1) / block;
-  hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE>), dim3(unsigned(grid)), dim3(block), 0, s, a);
+  const size_t lds = LaidOutHits<KIND, WIDE>::kStaged ? size_t(block / 64) * kRingFloats * sizeof(float) : 0;
+  hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE>), dim3(unsigned(grid)), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 

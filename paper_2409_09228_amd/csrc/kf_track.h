@@ -35,10 +35,41 @@ __device__ __forceinline__ uint32_t layer_step(float p[6], float C[21], Dir& d, 
   return fp ? fp : fu;
 }
 
+// Hits are staged through LDS: every wave owns a ring of kRing slots, one
+// layer of hits each (9 floats x 64 lanes, element-major so that both the
+// copy into LDS and the read back are lane-contiguous).  Layer k + kRing is
+// requested when layer k is read, so kRing layers are in flight per wave
+// without holding registers for them.  The copies go straight from memory to
+// LDS and complete in order, so reading slot k only needs the wave's
+// vector-memory counter down to the 9 (kRing - 1) copies issued after it.
+constexpr int kRing = 3;
+constexpr int kSlotFloats = 9 * 64;
+constexpr int kRingFloats = kRing * kSlotFloats;  // per wave
+
+// s_waitcnt with only the vector-memory count constrained (gfx9 encoding:
+// vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+template <int N>
+__device__ __forceinline__ void wait_vmem() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+// s_waitcnt lgkmcnt(0): this wave's LDS reads have returned
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14)); }
+
+__device__ __forceinline__ void read_slot(const float* slot, int lane, float m[3], float V[6]) {
+#pragma unroll
+  for (int e = 0; e < 3; ++e) m[e] = slot[e * 64 + lane];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) V[e] = slot[(3 + e) * 64 + lane];
+}
+
 // IO concepts used below:
 //   state.load(p, C) -> bool all-finite;  state.store(p, C)
-//   hits.load(k, m, V): hit of layer k (k < n_layers of the launch);
-//   hits.next(k): the layer index to prefetch after layer k (in bounds)
+//   hits.kStaged: hits go through the LDS ring
+//   hits.stage(j, slot): start copying the hit of layer min(j, the track's
+//     last layer) into the LDS slot (j wave-uniform; kStaged only)
+//   hits.load(l, m, V): read layer l into registers;  hits.next(k): the
+//     in-bounds layer to prefetch after layer k (register path)
 //   ckpt(k, p, C): called before layer k (may do nothing)
 struct NoCkpt {
   __device__ __forceinline__ void operator()(int, const float*, const float*) const {}
@@ -53,9 +84,16 @@ __device__ __forceinline__ uint32_t layer_at(int k, float p[6], float C[21], Dir
   return layer_step<GEOM, PREC, false>(p, C, d, m, V, target, b, chi2);
 }
 
+// The layer loop of one track.  Hits with Hits::kStaged (coalesced layouts)
+// come through this wave's LDS ring (kRingFloats of LDS at `ring`); the others
+// (AoS records, ragged gathers) are fetched one layer ahead into registers,
+// where multi-dword record loads serve them better than one-dword copies.
+// Every lane of the wave that runs a track calls this together (lanes
+// without one are inactive).
 template <int GEOM, int PREC, class State, class Hits, class Ckpt>
 __device__ __forceinline__ void run_track(const State& state, const Hits& hits, const Ckpt& ckpt, int nl,
-                                          const float* layer, float b, float& chi2_out, uint32_t& status_out) {
+                                          const float* layer, float b, float* ring, float& chi2_out,
+                                          uint32_t& status_out) {
   float p[6], C[21];
   uint32_t flags = state.load(p, C) ? 0u : S_NONFINITE;
   float chi2 = 0.0f;
@@ -63,25 +101,57 @@ __device__ __forceinline__ void run_track(const State& state, const Hits& hits, 
   if (!flags && nl > 0) {
     Dir d;
     dir_init(p, d);
-    // hits of the next layer are fetched one layer ahead; the first layer is
-    // peeled so that the loop body is the plane step that knows C's zero z row
-    float m[3], V[6], mn[3], Vn[6];
-    hits.load(0, m, V);
-    hits.load(hits.next(0, nl), mn, Vn);
-    ckpt(0, p, C);
-    flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
-    if (!flags) {
-      for (k = 1; k < nl; ++k) {
+    float m[3], V[6];
+    // the first layer is peeled so that the loop body is the plane step that
+    // knows C's zero z row
+    if constexpr (Hits::kStaged) {
+      const int lane = int(threadIdx.x & 63);
 #pragma unroll
-        for (int e = 0; e < 3; ++e) m[e] = mn[e];
+      for (int s = 0; s < kRing; ++s) hits.stage(s, ring + s * kSlotFloats);
+      wait_vmem<9 * (kRing - 1)>();
+      read_slot(ring, lane, m, V);
+      wait_lds();
+      hits.stage(kRing, ring);
+      ckpt(0, p, C);
+      flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
+      if (!flags) {
+        int s = 1;
+        for (k = 1; k < nl; ++k) {
+          float* slot = ring + s * kSlotFloats;
+          wait_vmem<9 * (kRing - 1)>();
+          read_slot(slot, lane, m, V);
+          wait_lds();
+          hits.stage(k + kRing, slot);
+          s = s + 1 == kRing ? 0 : s + 1;
+          ckpt(k, p, C);
+          const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+          if (f) {
+            flags = f;
+            break;
+          }
+        }
+      }
+      // no copy may still be writing the ring when the wave moves on
+      wait_vmem<0>();
+    } else {
+      float mn[3], Vn[6];
+      hits.load(0, m, V);
+      hits.load(hits.next(0), mn, Vn);
+      ckpt(0, p, C);
+      flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
+      if (!flags) {
+        for (k = 1; k < nl; ++k) {
 #pragma unroll
-        for (int e = 0; e < 6; ++e) V[e] = Vn[e];
-        hits.load(hits.next(k, nl), mn, Vn);
-        ckpt(k, p, C);
-        const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
-        if (f) {
-          flags = f;
-          break;
+          for (int e = 0; e < 3; ++e) m[e] = mn[e];
+#pragma unroll
+          for (int e = 0; e < 6; ++e) V[e] = Vn[e];
+          hits.load(hits.next(k), mn, Vn);
+          ckpt(k, p, C);
+          const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+          if (f) {
+            flags = f;
+            break;
+          }
         }
       }
     }
