@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 1
+#define KF_ABI_VERSION 2
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -120,7 +120,9 @@ enum {
   KF_S_NONFINITE = 1,       /* a NaN or Inf entered or came out of the update */
   KF_S_NOT_PD = 2,          /* S failed Sylvester's criterion */
   KF_S_NO_CROSSING = 4,     /* the helix never reaches the cylinder */
-  KF_S_NEWTON_RESIDUAL = 8  /* the cylinder iteration ended off the surface */
+  KF_S_NEWTON_RESIDUAL = 8, /* the cylinder iteration ended off the surface */
+  KF_S_BAD_HITS = 16        /* kf_propagate_update_batched: the track's hit rows fall
+                               outside [0, n_hits); the track is left as it came in */
 };
 #define KF_S_LAYERS_SHIFT 16
 
@@ -214,8 +216,10 @@ int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t lay
  *   par_in .. cov_out   as kf_propagate_update_z, in `layout`
  *   hit_pos, hit_cov    ragged per-track runs: track i's hit on its layer k
  *                       (k < n_layers_per_track[i]) is row hit_offset[i] + k of
- *                       hit_pos [H][3] and hit_cov [H][6]; every such row must exist
- *   hit_offset          [n_tracks] int64, 8-byte aligned
+ *                       hit_pos [n_hits][3] and hit_cov [n_hits][6]
+ *   hit_offset          [n_tracks] int64, 8-byte aligned; a track whose rows do
+ *                       not lie inside [0, n_hits) gets KF_S_BAD_HITS and no layer
+ *   n_hits              rows of hit_pos and hit_cov (>= 0)
  *   geom                [n_tracks] uint8: 0 plane (layer_z), any other value cylinder (layer_r)
  *   n_layers_per_track  [n_tracks] int32, clamped to [0, max_layers]
  *   layer_z, layer_r    HOST [max_layers] each: layer k of a track is plane
@@ -243,7 +247,7 @@ int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t lay
 int64_t kf_batched_workspace_size(int64_t n_tracks);
 kf_status_t kf_propagate_update_batched(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,
-    const float* hit_pos, const float* hit_cov, const int64_t* hit_offset, const uint8_t* geom,
+    const float* hit_pos, const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
     const int32_t* n_layers_per_track, const float* layer_z, const float* layer_r, int32_t max_layers,
     int64_t n_tracks, float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
     int32_t* status_out, void* workspace, int64_t workspace_bytes, const kf_tune_t* tune, void* stream);

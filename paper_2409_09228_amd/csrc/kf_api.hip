@@ -225,11 +225,13 @@ int64_t kf_batched_workspace_size(int64_t n_tracks) {
 
 kf_status_t kf_propagate_update_batched(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out, const float* hit_pos,
-    const float* hit_cov, const int64_t* hit_offset, const uint8_t* geom, const int32_t* n_layers_per_track,
+    const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
+    const int32_t* n_layers_per_track,
     const float* layer_z, const float* layer_r, int32_t max_layers, int64_t n_tracks, float bz_tesla,
     kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out, void* workspace,
     int64_t workspace_bytes, const kf_tune_t* tune, void* stream) {
-  if (n_tracks < 0 || n_tracks > KF_BATCHED_MAX_TRACKS || max_layers < 0 || max_layers > KF_MAX_LAYERS)
+  if (n_tracks < 0 || n_tracks > KF_BATCHED_MAX_TRACKS || max_layers < 0 || max_layers > KF_MAX_LAYERS ||
+      n_hits < 0)
     return KF_E_SHAPE;
   kf::TrackLayout tl;
   if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
@@ -265,6 +267,7 @@ kf_status_t kf_propagate_update_batched(
   a.hit_pos = hit_pos;
   a.hit_cov = hit_cov;
   a.hit_offset = hit_offset;
+  a.n_hits = n_hits;
   a.geom = geom;
   a.nlay = n_layers_per_track;
   a.chi2 = chi2_out;

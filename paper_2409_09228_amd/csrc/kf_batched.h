@@ -28,6 +28,7 @@ struct BatchedArgs {
   const float* hit_pos;
   const float* hit_cov;
   const int64_t* hit_offset;
+  int64_t n_hits;
   const uint8_t* geom;
   const int32_t* nlay;
   float* chi2;

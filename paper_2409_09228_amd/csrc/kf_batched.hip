@@ -27,6 +27,18 @@ __host__ __device__ inline int bucket_of(uint8_t geom, int nl, int max_layers) {
   return g * (KF_MAX_LAYERS + 1) + l;
 }
 
+// Layers track i runs: n_layers_per_track clamped to [0, L], or 0 when its hit
+// rows would fall outside [0, n_hits).
+__device__ __forceinline__ bool bad_hits(const BatchedArgs& a, int64_t i, int nl) {
+  const int64_t off = a.hit_offset[i];
+  return nl > 0 && (off < 0 || off > a.n_hits - nl);
+}
+__device__ __forceinline__ int track_layers(const BatchedArgs& a, int64_t i) {
+  int nl = a.nlay[i];
+  nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
+  return bad_hits(a, i, nl) ? 0 : nl;
+}
+
 __global__ void __launch_bounds__(256) kf_plan_clear(BatchedArgs a) {
   for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) {
     a.ws.bucket_count[b] = 0;
@@ -41,7 +53,7 @@ __global__ void __launch_bounds__(256) kf_plan_count(BatchedArgs a) {
   for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) hist[b] = 0;
   __syncthreads();
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x)
-    atomicAdd(&hist[bucket_of(a.geom[i], a.nlay[i], a.L)], 1);
+    atomicAdd(&hist[bucket_of(a.geom[i], track_layers(a, i), a.L)], 1);
   __syncthreads();
   for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x)
     if (hist[b]) atomicAdd(&a.ws.bucket_count[b], hist[b]);
@@ -93,7 +105,7 @@ __global__ void __launch_bounds__(256) kf_plan_scatter(BatchedArgs a) {
     const int64_t i = (int64_t(blockIdx.x) * kPer + u) * blockDim.x + threadIdx.x;
     bk[u] = -1;
     if (i < a.n) {
-      bk[u] = bucket_of(a.geom[i], a.nlay[i], a.L);
+      bk[u] = bucket_of(a.geom[i], track_layers(a, i), a.L);
       rk[u] = atomicAdd(&local[bk[u]], 1);
     }
   }
@@ -113,6 +125,7 @@ template <int KIND, bool WIDE>
 struct GatherState {
   const BatchedArgs& a;
   const Lanes<KIND, WIDE>& ln;
+  bool valid;  // false: a lane without a track of its own, which stores nothing
   __device__ __forceinline__ bool load(float p[6], float C[21]) const {
     ln.template ld_all<6>(ln.par, a.par_in, 0, p);
     ln.template ld_all<21>(ln.cov, a.cov_in, 0, C);
@@ -124,13 +137,14 @@ struct GatherState {
     return ok;
   }
   __device__ __forceinline__ void store(const float p[6], const float C[21]) const {
+    if (!valid) return;
     ln.template st_all<6>(ln.par, a.par_out, 0, p);
     ln.template st_all<21>(ln.cov, a.cov_out, 0, C);
   }
 };
 
 // hits of a track: rows hit_offset[t] .. hit_offset[t] + n_layers - 1 of the
-// ragged [H][3] and [H][6] arrays
+// ragged [n_hits][3] and [n_hits][6] arrays (the recompute path)
 struct RaggedHits {
   const float* hp;
   const float* hc;
@@ -138,25 +152,115 @@ struct RaggedHits {
     ld_rec<3>(hp + 3 * k, m);
     ld_rec<6>(hc + 6 * k, V);
   }
-  int last;  // the track's last layer (its work item's layer count - 1, wave-uniform)
-  // rows of different tracks are scattered: multi-dword record loads into
-  // registers, one layer ahead
-  static constexpr bool kStaged = false;
-  __device__ __forceinline__ int next(int k) const { return k < last ? k + 1 : k; }
-  __device__ __forceinline__ void stage(int, float*) const {}
 };
 
+// The ragged hits of a work item, staged through LDS in chunks of kChunk
+// layers, double-buffered.  A track's rows for one chunk are contiguous in
+// each array (kChunk * 12 and kChunk * 24 bytes), so the wave copies them
+// cooperatively: copy g of a chunk moves rows r = 64 g + lane, i.e. layer
+// r % kChunk of track r / kChunk, one element per instruction, straight into
+// LDS.  Fetching a track's rows for several layers at once uses most of every
+// line it touches; one lane reading its own 12- and 24-byte rows a layer at a
+// time fetched about five times the bytes it used.
+// Buffer: positions [kChunk][3][64] floats, then covariances [kChunk][6][64].
+constexpr int kChunk = 4;
+constexpr int kChunkFloats = kChunk * 64 * 9;
+constexpr int kChunkLdsFloats = 2 * kChunkFloats;  // per wave
+constexpr int kDmaLdsLimit = 65536;  // bytes of a block's LDS that copies into LDS can address
+static_assert(9 * kChunk < 64, "a chunk's copies must fit the wave's vector-memory counter");
+
+template <bool WIDE>
+struct ChunkRing {
+  static constexpr bool kCooperative = true;
+  const float* hp;  // array bases
+  const float* hc;
+  uint32_t hp_bytes, hc_bytes;
+  float* buf;   // kChunkLdsFloats of LDS, wave-uniform
+  int64_t h0;   // this lane's first row
+  int last;     // the item's layer count - 1 (wave-uniform)
+  int cnt;      // tracks in this wave's share of the item: lanes 0 .. cnt-1 (wave-uniform)
+  __device__ __forceinline__ void issue(int q, float* dst) const {
+    const int lane = int(threadIdx.x & 63);
+#pragma unroll
+    for (int g = 0; g < kChunk; ++g) {
+      const int r = g * 64 + lane;
+      int j = r / kChunk;
+      j = j < cnt ? j : cnt - 1;  // rows of lanes without a track: repeat a valid one
+      const int c = r % kChunk;
+      const int layer = q * kChunk + c < last ? q * kChunk + c : last;
+      float* dp = dst + g * 3 * 64;
+      float* dc = dst + kChunk * 3 * 64 + g * 6 * 64;
+      if constexpr (!WIDE) {
+        const uint32_t row = uint32_t(__shfl(int(h0), j, 64)) + uint32_t(layer);
+        const __amdgpu_buffer_rsrc_t rp = buf_rsrc(hp, hp_bytes);
+        const __amdgpu_buffer_rsrc_t rc = buf_rsrc(hc, hc_bytes);
+#pragma unroll
+        for (int e = 0; e < 3; ++e)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rp, (lds_void*)(dp + e * 64), 4, int(row * 12u), e * 4, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+          __builtin_amdgcn_raw_ptr_buffer_load_lds(rc, (lds_void*)(dc + e * 64), 4, int(row * 24u), e * 4, 0, 0);
+      } else {
+        const int lo = __shfl(int(uint32_t(uint64_t(h0))), j, 64);
+        const int hi = __shfl(int(uint32_t(uint64_t(h0) >> 32)), j, 64);
+        const int64_t row = int64_t((uint64_t(uint32_t(hi)) << 32) | uint32_t(lo)) + layer;
+        const float* sp = hp + row * 3;
+        const float* sc = hc + row * 6;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) __builtin_amdgcn_global_load_lds((gbl_void*)(sp + e), (lds_void*)(dp + e * 64), 4, 0, 0);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) __builtin_amdgcn_global_load_lds((gbl_void*)(sc + e), (lds_void*)(dc + e * 64), 4, 0, 0);
+      }
+    }
+  }
+  __device__ __forceinline__ void begin() { issue(0, buf); }
+  __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
+    const int q = k / kChunk, c = k % kChunk;
+    const float* cur = buf + (q & 1) * kChunkFloats;
+    if (c == 0) {
+      // the other buffer (chunk q - 1) has been read; refill it with chunk q + 1
+      wait_lds();
+      if ((q + 1) * kChunk <= last) {
+        issue(q + 1, buf + ((q + 1) & 1) * kChunkFloats);
+        wait_vmem<9 * kChunk>();
+      } else {
+        wait_vmem<0>();
+      }
+    }
+    const int r = int(threadIdx.x & 63) * kChunk + c;
+    const int g = r >> 6, l = r & 63;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) m[e] = cur[(g * 3 + e) * 64 + l];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) V[e] = cur[kChunk * 3 * 64 + (g * 6 + e) * 64 + l];
+  }
+  __device__ __forceinline__ void end() { wait_vmem<0>(); }
+};
+
+// Every lane of the wave calls this (the hits are copied cooperatively);
+// lanes past the item's last track (valid = false) repeat the item's first
+// track and store nothing.
 template <int PREC, int KIND, bool WIDE>
-__device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geom, int nl, float* ring) {
+__device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, bool valid, int geom, int nl, int cnt,
+                                        float* ring) {
   const Lanes<KIND, WIDE> ln(t, a.n, 1, a.lay);
   const int64_t h0 = a.hit_offset[t];
-  const RaggedHits hits{a.hit_pos + h0 * 3, a.hit_cov + h0 * 6, nl > 0 ? nl - 1 : 0};
+  const RaggedHits hits{a.hit_pos + h0 * 3, a.hit_cov + h0 * 6};
+  ChunkRing<WIDE> stager{a.hit_pos, a.hit_cov, uint32_t(a.n_hits * 12), uint32_t(a.n_hits * 24), ring, h0,
+                         nl > 0 ? nl - 1 : 0, cnt};
+  const GatherState<KIND, WIDE> state{a, ln, valid};
   float chi2;
   uint32_t status;
   if (geom == 0)
-    run_track<0, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_z, a.b, ring, chi2, status);
+    run_track<0, PREC>(state, hits, stager, NoCkpt{}, nl, a.layer_z, a.b, chi2, status);
   else
-    run_track<1, PREC>(GatherState<KIND, WIDE>{a, ln}, hits, NoCkpt{}, nl, a.layer_r, a.b, ring, chi2, status);
+    run_track<1, PREC>(state, hits, stager, NoCkpt{}, nl, a.layer_r, a.b, chi2, status);
+  if (!valid) return;
+  if (nl == 0) {
+    int nt = a.nlay[t];
+    nt = nt < 0 ? 0 : (nt > a.L ? a.L : nt);
+    if (bad_hits(a, t, nt)) status |= KF_S_BAD_HITS;
+  }
   if (a.chi2) a.chi2[t] = chi2;
   if (a.status) a.status[t] = int32_t(status);
 }
@@ -169,7 +273,8 @@ __device__ __forceinline__ void run_one(const BatchedArgs& a, int64_t t, int geo
 //                     (no atomics; the items are already longest-first)
 template <int PREC, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
-  float* ring = nullptr;  // ragged hits are not staged through LDS
+  extern __shared__ float kf_lds[];
+  float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kChunkLdsFloats;
   const int lane = threadIdx.x & 63;
   const int W = 64 * a.tpt;
   const int n_waves = int(gridDim.x * (blockDim.x >> 6));
@@ -182,8 +287,12 @@ __global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
     const int64_t slot0 = int64_t(item) * W;
     const int64_t end = int64_t(a.ws.bucket_base[b]) + a.ws.bucket_count[b];  // first slot past the bucket
     for (int u = 0; u < a.tpt; ++u) {
-      const int64_t slot = slot0 + u * 64 + lane;
-      if (slot < end) run_one<PREC, KIND, WIDE>(a, a.ws.perm[slot], geom, nl, ring);
+      const int64_t first = slot0 + u * 64;  // slots first .. first + 63 of this pass
+      const int cnt = end - first >= 64 ? 64 : int(end - first);
+      if (cnt <= 0) break;
+      const int64_t slot = first + lane;
+      const bool valid = slot < end;
+      run_one<PREC, KIND, WIDE>(a, a.ws.perm[valid ? slot : first], valid, geom, nl, cnt, ring);
     }
     if (a.schedule == KF_SCHED_STATIC) {
       item += n_waves;
@@ -202,7 +311,16 @@ static hipError_t launch_run(const BatchedArgs& a, int block, hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu <= 0)
     return hipErrorInvalidDevice;
-  const size_t lds = 0;
+  int max_lds = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return hipErrorInvalidDevice;
+  // copies straight into LDS address their destination through the low 16
+  // bits of M0: every wave's chunk buffers must lie in the block's first 64 KiB
+  if (max_lds > kDmaLdsLimit) max_lds = kDmaLdsLimit;
+  const int per_wave = kChunkLdsFloats * int(sizeof(float));
+  while (block > 64 && (block / 64) * per_wave > max_lds) block /= 2;  // the chunk buffers must fit a block
+  if (per_wave > max_lds) return hipErrorInvalidConfiguration;
+  const size_t lds = size_t(block / 64) * per_wave;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kf_batched_kernel<PREC, KIND, WIDE>, block, lds) !=
           hipSuccess ||
       per_cu <= 0)
@@ -232,7 +350,8 @@ hipError_t launch_batched(const BatchedArgs& a, int prec, int block, hipStream_t
   hipLaunchKernelGGL(kf_plan_scatter, dim3(g_scatter), dim3(256), 0, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const bool wide = needs_wide(a.n, 1, a.lay);
+  // 64-bit addressing when the state arrays or the ragged covariance rows span 4 GiB
+  const bool wide = needs_wide(a.n, 1, a.lay) || a.n_hits * 24 >= (int64_t(1) << 32);
   if (prec == 0) return launch_kinds<PREC_F32>(a, block, wide, s);
   if (prec == 1) return launch_kinds<PREC_F64>(a, block, wide, s);
   return launch_kinds<PREC_F64_JOSEPH>(a, block, wide, s);

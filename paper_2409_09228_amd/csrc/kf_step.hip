@@ -81,8 +81,16 @@ __global__ void __launch_bounds__(256) kf_step_kernel(const StepArgs a) {
   nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
   float chi2;
   uint32_t status;
-  run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, LaidOutHits<KIND, WIDE>(a, ln, nl),
-                        LaidOutCkpt<KIND, WIDE>{a, ln}, nl, a.layer, a.b, ring, chi2, status);
+  const LaidOutHits<KIND, WIDE> hits(a, ln, nl);
+  if constexpr (LaidOutHits<KIND, WIDE>::kStaged) {
+    LayerRing<LaidOutHits<KIND, WIDE>> stager(hits, ring);
+    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
+                          a.layer, a.b, chi2, status);
+  } else {
+    RegStager<LaidOutHits<KIND, WIDE>> stager(hits);
+    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
+                          a.layer, a.b, chi2, status);
+  }
   if (a.chi2) a.chi2[i] = chi2;
   if (a.status) a.status[i] = int32_t(status);
 }
@@ -91,6 +99,8 @@ template <int GEOM, int PREC, int KIND, bool WIDE>
 static hipError_t launch_one(int block, const StepArgs& a, hipStream_t s) {
   const int64_t grid = (a.n + block - 1) / block;
   const size_t lds = LaidOutHits<KIND, WIDE>::kStaged ? size_t(block / 64) * kRingFloats * sizeof(float) : 0;
+  // copies straight into LDS address it through the low 16 bits of M0
+  static_assert(4 * kRingFloats * sizeof(float) <= 65536, "a 256-thread block's rings must lie in 64 KiB of LDS");
   hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE>), dim3(unsigned(grid)), dim3(block), lds, s, a);
   return hipGetLastError();
 }

@@ -65,14 +65,62 @@ __device__ __forceinline__ void read_slot(const float* slot, int lane, float m[3
 
 // IO concepts used below:
 //   state.load(p, C) -> bool all-finite;  state.store(p, C)
-//   hits.kStaged: hits go through the LDS ring
-//   hits.stage(j, slot): start copying the hit of layer min(j, the track's
-//     last layer) into the LDS slot (j wave-uniform; kStaged only)
-//   hits.load(l, m, V): read layer l into registers;  hits.next(k): the
-//     in-bounds layer to prefetch after layer k (register path)
+//   hits.load(l, m, V): the hit of layer l into registers (the recompute path)
+//   stager: the hits of layers 0, 1, ... in order --
+//     begin(): start fetching (the track has at least one layer)
+//     get(k, m, V): layer k's hit
+//     end(): nothing of this track is in flight any more
+//     kCooperative: lanes fetch for each other, so every lane of the wave
+//       must call get() for every layer: the wave's tracks then share one
+//       layer count and a failing track does not leave the loop early
 //   ckpt(k, p, C): called before layer k (may do nothing)
 struct NoCkpt {
   __device__ __forceinline__ void operator()(int, const float*, const float*) const {}
+};
+
+// Hits fetched one layer ahead into registers (AoS records: multi-dword loads
+// serve them better than one-dword copies).  hits.next(k): the in-bounds
+// layer to prefetch after layer k.
+template <class Hits>
+struct RegStager {
+  static constexpr bool kCooperative = false;
+  const Hits& h;
+  float mn[3], Vn[6];
+  __device__ __forceinline__ explicit RegStager(const Hits& h_) : h(h_) {}
+  __device__ __forceinline__ void begin() { h.load(0, mn, Vn); }
+  __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
+#pragma unroll
+    for (int e = 0; e < 3; ++e) m[e] = mn[e];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) V[e] = Vn[e];
+    h.load(h.next(k), mn, Vn);
+  }
+  __device__ __forceinline__ void end() {}
+};
+
+// Element-major hits through this wave's LDS ring (kRingFloats at `ring`).
+// hits.stage(j, slot): start copying the hit of layer min(j, the track's last
+// layer) into the slot (j wave-uniform).
+template <class Hits>
+struct LayerRing {
+  static constexpr bool kCooperative = false;
+  const Hits& h;
+  float* ring;
+  int s;
+  __device__ __forceinline__ LayerRing(const Hits& h_, float* ring_) : h(h_), ring(ring_), s(0) {}
+  __device__ __forceinline__ void begin() {
+#pragma unroll
+    for (int i = 0; i < kRing; ++i) h.stage(i, ring + i * kSlotFloats);
+  }
+  __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
+    float* slot = ring + s * kSlotFloats;
+    wait_vmem<9 * (kRing - 1)>();
+    read_slot(slot, int(threadIdx.x & 63), m, V);
+    wait_lds();
+    h.stage(k + kRing, slot);
+    s = s + 1 == kRing ? 0 : s + 1;
+  }
+  __device__ __forceinline__ void end() { wait_vmem<0>(); }
 };
 
 // Layer k of a track: from the second layer on, a plane step knows the zero
@@ -84,77 +132,55 @@ __device__ __forceinline__ uint32_t layer_at(int k, float p[6], float C[21], Dir
   return layer_step<GEOM, PREC, false>(p, C, d, m, V, target, b, chi2);
 }
 
-// The layer loop of one track.  Hits with Hits::kStaged (coalesced layouts)
-// come through this wave's LDS ring (kRingFloats of LDS at `ring`); the others
-// (AoS records, ragged gathers) are fetched one layer ahead into registers,
-// where multi-dword record loads serve them better than one-dword copies.
-// Every lane of the wave that runs a track calls this together (lanes
-// without one are inactive).
-template <int GEOM, int PREC, class State, class Hits, class Ckpt>
-__device__ __forceinline__ void run_track(const State& state, const Hits& hits, const Ckpt& ckpt, int nl,
-                                          const float* layer, float b, float* ring, float& chi2_out,
+// The layer loop of one track.  Every lane of the wave that runs a track
+// calls this together (lanes without one are inactive); the stager's
+// wave-level waits rely on that.
+template <int GEOM, int PREC, class State, class Hits, class Stager, class Ckpt>
+__device__ __forceinline__ void run_track(const State& state, const Hits& hits, Stager& stager, const Ckpt& ckpt,
+                                          int nl, const float* layer, float b, float& chi2_out,
                                           uint32_t& status_out) {
   float p[6], C[21];
   uint32_t flags = state.load(p, C) ? 0u : S_NONFINITE;
   float chi2 = 0.0f;
   int k = 0;
-  if (!flags && nl > 0) {
+  if ((Stager::kCooperative || !flags) && nl > 0) {
     Dir d;
     dir_init(p, d);
     float m[3], V[6];
+    stager.begin();
     // the first layer is peeled so that the loop body is the plane step that
     // knows C's zero z row
-    if constexpr (Hits::kStaged) {
-      const int lane = int(threadIdx.x & 63);
-#pragma unroll
-      for (int s = 0; s < kRing; ++s) hits.stage(s, ring + s * kSlotFloats);
-      wait_vmem<9 * (kRing - 1)>();
-      read_slot(ring, lane, m, V);
-      wait_lds();
-      hits.stage(kRing, ring);
-      ckpt(0, p, C);
-      flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
-      if (!flags) {
-        int s = 1;
-        for (k = 1; k < nl; ++k) {
-          float* slot = ring + s * kSlotFloats;
-          wait_vmem<9 * (kRing - 1)>();
-          read_slot(slot, lane, m, V);
-          wait_lds();
-          hits.stage(k + kRing, slot);
-          s = s + 1 == kRing ? 0 : s + 1;
-          ckpt(k, p, C);
-          const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
-          if (f) {
-            flags = f;
-            break;
-          }
+    stager.get(0, m, V);
+    ckpt(0, p, C);
+    const uint32_t f0 = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
+    if (!flags) flags = f0;
+    if constexpr (Stager::kCooperative) {
+      // every lane walks all nl layers; the first failure (or a non-finite
+      // input) is kept, and the state after it, discarded below, no longer
+      // matters
+      int fail_at = flags ? 0 : nl;
+      for (k = 1; k < nl; ++k) {
+        stager.get(k, m, V);
+        ckpt(k, p, C);
+        const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+        if (f && !flags) {
+          flags = f;
+          fail_at = k;
         }
       }
-      // no copy may still be writing the ring when the wave moves on
-      wait_vmem<0>();
-    } else {
-      float mn[3], Vn[6];
-      hits.load(0, m, V);
-      hits.load(hits.next(0), mn, Vn);
-      ckpt(0, p, C);
-      flags = layer_step<GEOM, PREC, false>(p, C, d, m, V, layer[0], b, chi2);
-      if (!flags) {
-        for (k = 1; k < nl; ++k) {
-#pragma unroll
-          for (int e = 0; e < 3; ++e) m[e] = mn[e];
-#pragma unroll
-          for (int e = 0; e < 6; ++e) V[e] = Vn[e];
-          hits.load(hits.next(k), mn, Vn);
-          ckpt(k, p, C);
-          const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
-          if (f) {
-            flags = f;
-            break;
-          }
+      k = fail_at;
+    } else if (!flags) {
+      for (k = 1; k < nl; ++k) {
+        stager.get(k, m, V);
+        ckpt(k, p, C);
+        const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+        if (f) {
+          flags = f;
+          break;
         }
       }
     }
+    stager.end();
   }
   const int done = k;
   if (flags) {

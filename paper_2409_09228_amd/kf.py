@@ -33,6 +33,7 @@ S_NONFINITE = 1
 S_NOT_PD = 2
 S_NO_CROSSING = 4
 S_NEWTON_RESIDUAL = 8
+S_BAD_HITS = 16
 LAYERS_SHIFT = 16
 
 
@@ -97,7 +98,8 @@ def lib():
         L.kf_checkpoint_floats.restype = i64
         L.kf_batched_workspace_size.argtypes = [i64]
         L.kf_batched_workspace_size.restype = i64
-        L.kf_propagate_update_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32, i64, f32, Layout,
+        L.kf_propagate_update_batched.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32, i64, f32,
+                                                  Layout,
                                                   ctypes.c_uint32, vp, vp, vp, i64, ctypes.POINTER(Tune), vp]
         L.kf_propagate_update_batched.restype = ctypes.c_int
         L.kf_batched_release.restype = None
@@ -357,7 +359,8 @@ class BatchedLauncher:
         with torch.cuda.device(st["par"].device):
             sp = _stream(stream)
         self._args = (_ptr(st["par"]), _ptr(st["cov"]), _ptr(out[0]), _ptr(out[1]), _ptr(st["hit_pos"]),
-                      _ptr(st["hit_cov"]), _ptr(st["hit_offset"]), _ptr(st["geom"]), _ptr(st["nlay"]),
+                      _ptr(st["hit_cov"]), _ptr(st["hit_offset"]), int(st["hit_pos"].shape[0]), _ptr(st["geom"]),
+                      _ptr(st["nlay"]),
                       self._lz.ctypes.data_as(ctypes.c_void_p), self._lr.ctypes.data_as(ctypes.c_void_p),
                       int(st["L"]), int(n), float(st["bz"]), Layout(*st["layout"]), int(flags), _ptr(chi2),
                       _ptr(status), _ptr(self._ws), int(self._ws.numel()),

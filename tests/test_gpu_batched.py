@@ -149,6 +149,32 @@ def test_batched_edge_cases(kf, uneven):
     np.testing.assert_array_equal(g1[3], r1[3])
 
 
+def test_hit_rows_outside_the_arrays_are_flagged(kf, uneven):
+    """A track whose rows would leave [0, n_hits) gets KF_S_BAD_HITS, applies no
+    layer and keeps its input state; the other tracks are unaffected."""
+    sub = S.subset(uneven, np.arange(500))
+    st = kf.stage_batched(sub, kf.AOS)
+    ref = _logical(kf, st, kf.run_batched(st))
+    n_hits = st["hit_pos"].shape[0]
+    off = st["hit_offset"].clone()
+    nl = sub["nlay"]
+    bad = [int(np.nonzero(nl > 0)[0][0]), int(np.nonzero(nl > 3)[0][-1]), 7]
+    off[bad[0]] = -1
+    off[bad[1]] = n_hits - int(nl[bad[1]]) + 1   # last row one past the end
+    off[bad[2]] = 1 << 40
+    st2 = dict(st, hit_offset=off)
+    got = _logical(kf, st2, kf.run_batched(st2))
+    for i in bad:
+        if nl[i] == 0:
+            continue
+        assert got[3][i] == kf.S_BAD_HITS, (i, got[3][i])
+        np.testing.assert_array_equal(got[0][i], sub["par"][i].astype(np.float32))
+        assert got[2][i] == 0.0
+    keep = np.setdiff1d(np.arange(500), bad)
+    for k in range(4):
+        np.testing.assert_array_equal(got[k][keep], ref[k][keep])
+
+
 def test_workspace_too_small_is_rejected(kf, uneven):
     sub = S.subset(uneven, np.arange(1000))
     st = kf.stage_batched(sub, kf.AOS)
