@@ -237,7 +237,7 @@ int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t lay
  * On the device each call sorts the tracks into work items of 64 (x
  * tracks_per_thread) tracks with one geometry and one layer count, ordered by
  * decreasing cost, and a grid that just fills the GPU pulls items from an
- * atomic counter.  Unless KF_F_NO_GRAPH is set the five kernels of a call are
+ * atomic counter.  Unless KF_F_NO_GRAPH is set the four kernels of a call are
  * captured once into a hipGraph, cached by the call's arguments (up to 32
  * graphs), and replayed on `stream` by later identical calls -- so buffers
  * passed once must stay valid while their graph is cached (kf_batched_release

@@ -150,7 +150,7 @@ kf_status_t batched_via_graph(const kf::BatchedArgs& a, int prec, int block, int
     hipGraph_t graph = nullptr;
     const hipError_t ce = hipStreamEndCapture(cs, &graph);
     if (le != hipSuccess || ce != hipSuccess || !graph) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return KF_E_LAUNCH;
     }
     const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

@@ -15,8 +15,8 @@ struct BatchedWorkspace {
   int32_t* bucket_count;   // [KF_NBUCKETS] tracks per bucket
   int32_t* bucket_cursor;  // [KF_NBUCKETS] scatter cursors
   int32_t* bucket_base;    // [KF_NBUCKETS] first slot of each bucket
-  int32_t* counter;        // [4]: next item, number of items
-  int32_t* item_bucket;    // [max items] bucket id of each item
+  int32_t* counter;        // [4]: next item, number of items, count blocks done
+  int32_t* item_base;      // [KF_NBUCKETS + 1] first item of each bucket order position
   int32_t* perm;           // [max slots] track index per slot
 };
 
@@ -51,7 +51,7 @@ int64_t batched_workspace_bytes(int64_t n);
 // Carve the workspace; false if it is too small.
 bool batched_carve(void* ws, int64_t bytes, int64_t n, BatchedWorkspace* out);
 void bucket_order(int32_t order[KF_NBUCKETS]);
-// Enqueue the four planning kernels and the persistent run.
+// Enqueue the three planning kernels and the persistent run.
 hipError_t launch_batched(const BatchedArgs& a, int prec, int block, hipStream_t s);
 
 }  // namespace kf

@@ -2,17 +2,18 @@
 //
 // Planning, on the device, every call (so the whole call can be captured once
 // into a hipGraph and replayed):
-//   1. clear      zero the bucket counters and the work counter
-//   2. count      histogram of tracks over buckets (geometry, layer count)
-//   3. scan       lay the buckets out in decreasing estimated cost (layer
-//                 count, with a cylinder layer costing about twice a plane
-//                 layer), each rounded up to whole work items of W = 64 *
-//                 tracks_per_thread tracks; one bucket id per item (slots past
-//                 a bucket's count are skipped)
-//   4. scatter    track indices into their bucket's slots
-//   5. run        persistent waves claim items from an atomic counter, longest
-//                 first; an item holds tracks of one geometry and one layer
-//                 count, so a wave never diverges on either.
+//   1. clear      zero the bucket counters and the work counters
+//   2. count      histogram of tracks over buckets (geometry, layer count);
+//                 its last block lays the buckets out in decreasing estimated
+//                 cost (layer count, a cylinder layer costing about twice a
+//                 plane layer), each rounded up to whole work items of W = 64 *
+//                 tracks_per_thread tracks (slots past a bucket's count are
+//                 skipped)
+//   3. scatter    track indices into their bucket's slots
+//   4. run        persistent waves claim items, longest first, and find an
+//                 item's bucket by binary search over the item layout; an item
+//                 holds tracks of one geometry and one layer count, so a wave
+//                 never diverges on either.
 // A work item's tracks are gathered by index: their state through the track
 // layout, their hits from ragged per-track runs.
 #include "kf_batched.h"
@@ -47,9 +48,15 @@ __global__ void __launch_bounds__(256) kf_plan_clear(BatchedArgs a) {
   if (threadIdx.x < 4) a.ws.counter[threadIdx.x] = 0;
 }
 
-// Per-block histograms in LDS, one global atomic per (block, bucket).
+// Per-block histograms in LDS, one global atomic per (block, bucket).  The
+// last block to finish (a done-counter after a fence) then lays the buckets
+// out: in the order given by a.order (decreasing cost), each rounded up to
+// whole items of W = 64 * tracks_per_thread slots; it writes every bucket's
+// first slot, the first item of every order position, and the item count.
 __global__ void __launch_bounds__(256) kf_plan_count(BatchedArgs a) {
   __shared__ int hist[KF_NBUCKETS];
+  __shared__ int base_item[KF_NBUCKETS + 1];
+  __shared__ bool last;
   for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x) hist[b] = 0;
   __syncthreads();
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n; i += int64_t(gridDim.x) * blockDim.x)
@@ -57,37 +64,34 @@ __global__ void __launch_bounds__(256) kf_plan_count(BatchedArgs a) {
   __syncthreads();
   for (int b = threadIdx.x; b < KF_NBUCKETS; b += blockDim.x)
     if (hist[b]) atomicAdd(&a.ws.bucket_count[b], hist[b]);
-}
-
-// One block.  Buckets in the order given by a.order (decreasing cost); the
-// counts are read in parallel into LDS, scanned there, and every item's
-// bucket id is written in parallel (binary search over the item bases).
-__global__ void __launch_bounds__(256) kf_plan_scan(BatchedArgs a) {
-  __shared__ int cnt[KF_NBUCKETS];
-  __shared__ int base_item[KF_NBUCKETS + 1];
-  const int W = 64 * a.tpt;
-  const int wsh = a.tpt == 2 ? 7 : 6;  // log2(W)
-  for (int j = threadIdx.x; j < KF_NBUCKETS; j += blockDim.x) cnt[j] = a.ws.bucket_count[a.order[j]];
+  // The counts are device-scope atomics, performed where every XCD sees them:
+  // once this block's have been acknowledged (all counters waited to zero) it
+  // may report itself done -- no cache write-back is needed for atomics, and a
+  // full fence here (an L2 write-back on this part) costs more than the scan.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.ws.counter[2], 1) == int(gridDim.x) - 1;
+  __syncthreads();
+  if (!last) return;
+  // every block's counts are in; read them at the same place (atomics), in cost order
+  for (int j = threadIdx.x; j < KF_NBUCKETS; j += blockDim.x) hist[j] = atomicAdd(&a.ws.bucket_count[a.order[j]], 0);
   __syncthreads();
   if (threadIdx.x == 0) {
+    const int wsh = a.tpt == 2 ? 7 : 6;  // log2(W)
+    const int W = 1 << wsh;
     int items = 0;
     for (int j = 0; j < KF_NBUCKETS; ++j) {
       base_item[j] = items;
-      items += (cnt[j] + W - 1) >> wsh;
+      items += (hist[j] + W - 1) >> wsh;
     }
     base_item[KF_NBUCKETS] = items;
     a.ws.counter[1] = items;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < KF_NBUCKETS; j += blockDim.x) a.ws.bucket_base[a.order[j]] = base_item[j] * W;
-  const int n_items = base_item[KF_NBUCKETS];
-  for (int it = threadIdx.x; it < n_items; it += blockDim.x) {
-    int lo = 0, hi = KF_NBUCKETS - 1;  // last j with base_item[j] <= it
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (base_item[mid] <= it) lo = mid; else hi = mid - 1;
-    }
-    a.ws.item_bucket[it] = a.order[lo];
+  const int W = 64 * a.tpt;
+  for (int j = threadIdx.x; j <= KF_NBUCKETS; j += blockDim.x) {
+    a.ws.item_base[j] = base_item[j];
+    if (j < KF_NBUCKETS) a.ws.bucket_base[a.order[j]] = base_item[j] * W;
   }
 }
 
@@ -163,11 +167,19 @@ struct RaggedHits {
 // line it touches; one lane reading its own 12- and 24-byte rows a layer at a
 // time fetched about five times the bytes it used.
 // Buffer: positions [kChunk][3][64] floats, then covariances [kChunk][6][64].
-constexpr int kChunk = 4;
+#ifndef KF_CHUNK_LAYERS
+#define KF_CHUNK_LAYERS 4
+#endif
+#ifndef KF_CHUNK_BUFS
+#define KF_CHUNK_BUFS 2
+#endif
+constexpr int kChunk = KF_CHUNK_LAYERS;
+constexpr int kChunkBufs = KF_CHUNK_BUFS;  // 2: the next chunk fetched a chunk ahead; 1: a layer ahead
 constexpr int kChunkFloats = kChunk * 64 * 9;
-constexpr int kChunkLdsFloats = 2 * kChunkFloats;  // per wave
+constexpr int kChunkLdsFloats = kChunkBufs * kChunkFloats;  // per wave
 constexpr int kDmaLdsLimit = 65536;  // bytes of a block's LDS that copies into LDS can address
-static_assert(9 * kChunk < 64, "a chunk's copies must fit the wave's vector-memory counter");
+static_assert(kChunkBufs == 1 || 9 * kChunk < 64, "a chunk's copies must fit the wave's vector-memory counter");
+static_assert(kChunkBufs == 1 || kChunkBufs == 2, "one or two chunk buffers");
 
 template <bool WIDE>
 struct ChunkRing {
@@ -216,15 +228,19 @@ struct ChunkRing {
   __device__ __forceinline__ void begin() { issue(0, buf); }
   __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
     const int q = k / kChunk, c = k % kChunk;
-    const float* cur = buf + (q & 1) * kChunkFloats;
+    const float* cur = kChunkBufs == 2 ? buf + (q & 1) * kChunkFloats : buf;
     if (c == 0) {
-      // the other buffer (chunk q - 1) has been read; refill it with chunk q + 1
-      wait_lds();
-      if ((q + 1) * kChunk <= last) {
-        issue(q + 1, buf + ((q + 1) & 1) * kChunkFloats);
-        wait_vmem<9 * kChunk>();
+      if constexpr (kChunkBufs == 2) {
+        // the other buffer (chunk q - 1) has been read; refill it with chunk q + 1
+        wait_lds();
+        if ((q + 1) * kChunk <= last) {
+          issue(q + 1, buf + ((q + 1) & 1) * kChunkFloats);
+          wait_vmem<9 * kChunk>();
+        } else {
+          wait_vmem<0>();
+        }
       } else {
-        wait_vmem<0>();
+        wait_vmem<0>();  // chunk q, requested during the chunk before
       }
     }
     const int r = int(threadIdx.x & 63) * kChunk + c;
@@ -233,6 +249,13 @@ struct ChunkRing {
     for (int e = 0; e < 3; ++e) m[e] = cur[(g * 3 + e) * 64 + l];
 #pragma unroll
     for (int e = 0; e < 6; ++e) V[e] = cur[kChunk * 3 * 64 + (g * 6 + e) * 64 + l];
+    if constexpr (kChunkBufs == 1) {
+      // the chunk's last layer is read: refill the buffer with the next chunk
+      if (c == kChunk - 1 && (q + 1) * kChunk <= last) {
+        wait_lds();
+        issue(q + 1, buf);
+      }
+    }
   }
   __device__ __forceinline__ void end() { wait_vmem<0>(); }
 };
@@ -275,13 +298,21 @@ template <int PREC, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_batched_kernel(const BatchedArgs a) {
   extern __shared__ float kf_lds[];
   float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kChunkLdsFloats;
+  __shared__ int item_base[KF_NBUCKETS + 1];  // first item of each order position
+  for (int j = threadIdx.x; j <= KF_NBUCKETS; j += blockDim.x) item_base[j] = a.ws.item_base[j];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int W = 64 * a.tpt;
   const int n_waves = int(gridDim.x * (blockDim.x >> 6));
-  const int n_items = a.ws.counter[1];
+  const int n_items = item_base[KF_NBUCKETS];
   int item = int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
   while (item < n_items) {
-    const int b = a.ws.item_bucket[item];
+    int lo = 0, hi = KF_NBUCKETS - 1;  // the last order position whose first item is <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (item_base[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const int b = a.order[lo];
     const int geom = b / (KF_MAX_LAYERS + 1);
     const int nl = b % (KF_MAX_LAYERS + 1);
     const int64_t slot0 = int64_t(item) * W;
@@ -346,7 +377,6 @@ hipError_t launch_batched(const BatchedArgs& a, int prec, int block, hipStream_t
   const unsigned g_scatter = unsigned((a.n + 1023) / 1024 > 0 ? (a.n + 1023) / 1024 : 1);
   hipLaunchKernelGGL(kf_plan_clear, dim3(1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(kf_plan_count, dim3(g_count), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(kf_plan_scan, dim3(1), dim3(256), 0, s, a);
   hipLaunchKernelGGL(kf_plan_scatter, dim3(g_scatter), dim3(256), 0, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -382,30 +412,23 @@ namespace kf {
 
 static int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
-static void sizes(int64_t n, int64_t* items, int64_t* slots) {
-  *items = (n + 63) / 64 + KF_NBUCKETS;           // most items: 64-track items
-  *slots = n + int64_t(KF_NBUCKETS + 1) * 128;    // most slots: 128-track items
-}
+// most slots: every bucket padded to whole 128-track items
+static int64_t max_slots(int64_t n) { return n + int64_t(KF_NBUCKETS + 1) * 128; }
 
 int64_t batched_workspace_bytes(int64_t n) {
-  int64_t items, slots;
-  sizes(n, &items, &slots);
-  return align256(4 * (3 * KF_NBUCKETS + 4)) + align256(4 * items) + align256(4 * slots);
+  return align256(4 * (4 * KF_NBUCKETS + 5)) + align256(4 * max_slots(n));
 }
 
 bool batched_carve(void* ws, int64_t bytes, int64_t n, BatchedWorkspace* out) {
   if (!ws || bytes < batched_workspace_bytes(n)) return false;
-  int64_t items, slots;
-  sizes(n, &items, &slots);
   char* p = static_cast<char*>(ws);
   int32_t* head = reinterpret_cast<int32_t*>(p);
   out->bucket_count = head;
   out->bucket_cursor = head + KF_NBUCKETS;
   out->bucket_base = head + 2 * KF_NBUCKETS;
   out->counter = head + 3 * KF_NBUCKETS;
-  p += align256(4 * (3 * KF_NBUCKETS + 4));
-  out->item_bucket = reinterpret_cast<int32_t*>(p);
-  p += align256(4 * items);
+  out->item_base = head + 3 * KF_NBUCKETS + 4;
+  p += align256(4 * (4 * KF_NBUCKETS + 5));
   out->perm = reinterpret_cast<int32_t*>(p);
   return true;
 }

@@ -19,6 +19,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkf.so")
+# another build of the same library (a variant's timing) may be named here
+LIB_PATH = os.environ.get("KF_LIB", LIB_PATH)
 
 KF_OK = 0
 KF_SOA = 0
