@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 2
+#define KF_ABI_VERSION 3
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -144,10 +144,13 @@ enum {
  *   flags             0 (FP32 throughout) or KF_F_* bits
  *   chi2_out          [n_tracks] summed chi-square of the applied layers, or NULL
  *   status_out        [n_tracks] status words, or NULL
- *   ckpt_out          NULL, or [n_layers][27] per track in `layout` (per-layer
- *                     form, E = 27): the state (6 parameters, then the 21
- *                     covariance numbers) that entered layer l; layers a track
- *                     does not reach are left untouched.  Used by kf_chi2_backward.
+ *   ckpt_out          NULL, or [ceil(n_layers / ckpt_every)][27] per track in
+ *                     `layout` (per-layer form, E = 27): slot j holds the state
+ *                     (6 parameters, then the 21 covariance numbers) that
+ *                     entered layer j * ckpt_every; slots of layers a track
+ *                     does not reach are left untouched.  Used by kf_chi2_backward_z.
+ *   ckpt_every        1, 2, 4, .. 64 (0 means 1): the checkpoint stride in layers
+ *                     (anything else: KF_E_SHAPE)
  *   tune              NULL or a launch shape
  *
  * The plane is reached after the transverse path s = (z_l - z) tan(theta);
@@ -158,7 +161,7 @@ kf_status_t kf_propagate_update_z(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,
     const float* hit_pos, const float* hit_cov, const float* layer_z, int32_t n_layers,
     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
-    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out,
+    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out, int32_t ckpt_every,
     const kf_tune_t* tune, void* stream);
 
 /*
@@ -170,13 +173,14 @@ kf_status_t kf_propagate_update_z(
  * cylinder at all (KF_S_NO_CROSSING otherwise).  A crossing whose radius still
  * misses r_l by more than 1e-4 * r_l after the five steps sets
  * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z; ckpt_out is
- * not supported here and must be NULL (KF_E_UNSUPPORTED).
+ * not supported here and must be NULL (KF_E_UNSUPPORTED); ckpt_every is then
+ * ignored.
  */
 kf_status_t kf_propagate_update_r(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,
     const float* hit_pos, const float* hit_cov, const float* layer_r, int32_t n_layers,
     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
-    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out,
+    uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out, int32_t ckpt_every,
     const kf_tune_t* tune, void* stream);
 
 /*
@@ -194,6 +198,10 @@ kf_status_t kf_propagate_update_r(
  *   ckpt           the forward's ckpt_out, or NULL to recompute the entering
  *                  state of every layer from the seed (no extra memory,
  *                  O(layers^2) work instead of O(layers))
+ *   ckpt_every     the forward's checkpoint stride s: the state entering layer
+ *                  k is recomputed from slot k / s through layers
+ *                  s * (k / s) .. k - 1 (up to s - 1 forward steps; s times
+ *                  less memory than s = 1)
  *   grad_chi2      [n_tracks] dL/dchi2_i
  *   grad_hit_pos   per-layer [n_layers][3] in `layout`; layers a track did not
  *                  apply get 0
@@ -203,10 +211,12 @@ kf_status_t kf_propagate_update_r(
 kf_status_t kf_chi2_backward_z(
     const float* par_in, const float* cov_in, const float* hit_pos, const float* hit_cov,
     const float* layer_z, int32_t n_layers, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
-    const int32_t* status_fwd, const float* ckpt, const float* grad_chi2, float* grad_hit_pos,
-    float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream);
-/* Floats of a checkpoint buffer for kf_propagate_update_z / kf_chi2_backward_z. */
-int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t layout);
+    const int32_t* status_fwd, const float* ckpt, int32_t ckpt_every, const float* grad_chi2,
+    float* grad_hit_pos, float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream);
+/* Floats of a checkpoint buffer for kf_propagate_update_z / kf_chi2_backward_z:
+ * ceil(n_layers / ckpt_every) per-layer slots of 27 floats per track in
+ * `layout`; 0 for invalid arguments. */
+int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_every, kf_layout_t layout);
 
 /*
  * kf_propagate_update_batched -- tracks of both geometries and uneven layer

@@ -198,7 +198,7 @@ template <int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_adjoint_z_kernel(const AdjointArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
+  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.Lck);
   const int L = a.L;
   int done = int(uint32_t(a.status[i]) >> KF_S_LAYERS_SHIFT);
   done = done > L ? L : done;
@@ -211,22 +211,28 @@ __global__ void __launch_bounds__(256) kf_adjoint_z_kernel(const AdjointArgs a) 
 #pragma unroll
   for (int e = 0; e < 21; ++e) aP[e] = 0.0f;
   for (int k = done - 1; k >= 0; --k) {
+    // the state entering layer k: from the checkpoint slot that covers it (or
+    // the seed), then forward through layers j0 .. k-1
     float p[6], P[21];
+    int j0 = 0;
     if (a.ckpt) {
+      const int c = k >> a.ck_shift;
+      j0 = c << a.ck_shift;
       float s[27];
-      ln.template ld_all<27>(ln.ck, a.ckpt, k, s);
+      ln.template ld_all<27>(ln.ck, a.ckpt, c, s);
 #pragma unroll
       for (int e = 0; e < 6; ++e) p[e] = s[e];
 #pragma unroll
       for (int e = 0; e < 21; ++e) P[e] = s[6 + e];
     } else {
-      // recompute: the seed through layers 0..k-1
       ln.template ld_all<6>(ln.par, a.par_in, 0, p);
       ln.template ld_all<21>(ln.cov, a.cov_in, 0, P);
+    }
+    if (j0 < k) {
       float chi2 = 0.0f;
       Dir d;
       dir_init(p, d);
-      for (int j = 0; j < k; ++j) {
+      for (int j = j0; j < k; ++j) {
         float m[3], V[6];
         ln.template ld_all<3>(ln.hp, a.hit_pos, j, m);
         ln.template ld_all<6>(ln.hc, a.hit_cov, j, V);

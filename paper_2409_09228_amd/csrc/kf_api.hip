@@ -48,12 +48,22 @@ kf_status_t device_ok() {
   return known[dev] == 1 ? KF_OK : KF_E_DEVICE;
 }
 
+// log2 of a checkpoint stride (0 -> 1; 1, 2, 4, .. 64), or -1
+int ckpt_shift(int32_t every) {
+  if (every == 0) return 0;
+  for (int sh = 0; sh <= 6; ++sh)
+    if (every == (1 << sh)) return sh;
+  return -1;
+}
+
 kf_status_t step(int geom, const float* par_in, const float* cov_in, float* par_out, float* cov_out,
                  const float* hit_pos, const float* hit_cov, const float* layers, int32_t n_layers,
                  const int32_t* nlay, int64_t n_tracks, float bz, kf_layout_t layout, uint32_t flags,
-                 float* chi2_out, int32_t* status_out, float* ckpt_out, const kf_tune_t* tune,
-                 void* stream) {
+                 float* chi2_out, int32_t* status_out, float* ckpt_out, int32_t ckpt_every,
+                 const kf_tune_t* tune, void* stream) {
   if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  const int ck_shift = ckpt_shift(ckpt_every);
+  if (ckpt_out && ck_shift < 0) return KF_E_SHAPE;
   kf::TrackLayout tl;
   if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
   if (flags & ~uint32_t(KF_F_PRECISION)) return KF_E_FLAGS;
@@ -89,6 +99,8 @@ kf_status_t step(int geom, const float* par_in, const float* cov_in, float* par_
   a.ckpt = ckpt_out;
   a.n = n_tracks;
   a.L = n_layers;
+  a.ck_shift = ckpt_out ? ck_shift : 0;
+  a.Lck = ckpt_out ? (n_layers + (1 << ck_shift) - 1) >> ck_shift : n_layers;
   a.lay = tl;
   a.b = float(kCLight * double(bz));
   for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
@@ -174,9 +186,11 @@ extern "C" {
 kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const float* hit_pos,
                                const float* hit_cov, const float* layer_z, int32_t n_layers, int64_t n_tracks,
                                float bz_tesla, kf_layout_t layout, const int32_t* status_fwd, const float* ckpt,
-                               const float* grad_chi2, float* grad_hit_pos, float* grad_par_in,
-                               float* grad_cov_in, const kf_tune_t* tune, void* stream) {
+                               int32_t ckpt_every, const float* grad_chi2, float* grad_hit_pos,
+                               float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream) {
   if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  const int ck_shift = ckpt_shift(ckpt_every);
+  if (ckpt && ck_shift < 0) return KF_E_SHAPE;
   kf::TrackLayout tl;
   if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
   int block = 256;
@@ -206,6 +220,8 @@ kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const f
   a.grad_cov = grad_cov_in;
   a.n = n_tracks;
   a.L = n_layers;
+  a.ck_shift = ckpt ? ck_shift : 0;
+  a.Lck = ckpt ? (n_layers + (1 << ck_shift) - 1) >> ck_shift : n_layers;
   a.lay = tl;
   a.b = float(kCLight * double(bz_tesla));
   for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layer_z[l] : 0.0f;
@@ -213,10 +229,11 @@ kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const f
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 
-int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, kf_layout_t layout) {
+int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_every, kf_layout_t layout) {
   kf::TrackLayout tl;
-  if (n_tracks < 0 || n_layers <= 0 || !layout_ok(layout, &tl)) return 0;
-  return kf::layout_floats(n_tracks, 27, n_layers, tl);
+  const int sh = ckpt_shift(ckpt_every);
+  if (n_tracks < 0 || n_layers <= 0 || sh < 0 || !layout_ok(layout, &tl)) return 0;
+  return kf::layout_floats(n_tracks, 27, (n_layers + (1 << sh) - 1) >> sh, tl);
 }
 
 int64_t kf_batched_workspace_size(int64_t n_tracks) {
@@ -307,18 +324,20 @@ kf_status_t kf_propagate_update_z(const float* par_in, const float* cov_in, floa
                                   const float* hit_pos, const float* hit_cov, const float* layer_z,
                                   int32_t n_layers, const int32_t* n_layers_per_track, int64_t n_tracks,
                                   float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
-                                  int32_t* status_out, float* ckpt_out, const kf_tune_t* tune, void* stream) {
+                                  int32_t* status_out, float* ckpt_out, int32_t ckpt_every, const kf_tune_t* tune,
+                                  void* stream) {
   return step(0, par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, layer_z, n_layers, n_layers_per_track,
-              n_tracks, bz_tesla, layout, flags, chi2_out, status_out, ckpt_out, tune, stream);
+              n_tracks, bz_tesla, layout, flags, chi2_out, status_out, ckpt_out, ckpt_every, tune, stream);
 }
 
 kf_status_t kf_propagate_update_r(const float* par_in, const float* cov_in, float* par_out, float* cov_out,
                                   const float* hit_pos, const float* hit_cov, const float* layer_r,
                                   int32_t n_layers, const int32_t* n_layers_per_track, int64_t n_tracks,
                                   float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
-                                  int32_t* status_out, float* ckpt_out, const kf_tune_t* tune, void* stream) {
+                                  int32_t* status_out, float* ckpt_out, int32_t ckpt_every, const kf_tune_t* tune,
+                                  void* stream) {
   return step(1, par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, layer_r, n_layers, n_layers_per_track,
-              n_tracks, bz_tesla, layout, flags, chi2_out, status_out, ckpt_out, tune, stream);
+              n_tracks, bz_tesla, layout, flags, chi2_out, status_out, ckpt_out, ckpt_every, tune, stream);
 }
 
 kf_status_t kf_pack(const float* src_soa, float* dst, int32_t n_elem, int32_t n_layers_or_1, int64_t n_tracks,

@@ -28,6 +28,8 @@ struct StepArgs {
   float* ckpt;
   int64_t n;
   int32_t L;
+  int32_t ck_shift;  // log2 of the checkpoint stride
+  int32_t Lck;       // checkpoint slots per track: ceil(L / stride)
   TrackLayout lay;
   float b;  // 0.00299792458 * Bz
   float layer[KF_MAX_LAYERS];
@@ -38,7 +40,7 @@ struct AdjointArgs {
   const float* cov_in;
   const float* hit_pos;
   const float* hit_cov;
-  const float* ckpt;       // per-layer entering states, or NULL: recompute
+  const float* ckpt;       // entering states of every stride-th layer, or NULL: recompute
   const int32_t* status;   // the forward's status words
   const float* grad_chi2;  // dL/dchi2_i
   float* grad_hit;         // dL/dm, per layer
@@ -46,6 +48,8 @@ struct AdjointArgs {
   float* grad_cov;         // dL/dC0 or NULL
   int64_t n;
   int32_t L;
+  int32_t ck_shift;        // log2 of the checkpoint stride
+  int32_t Lck;             // checkpoint slots per track
   TrackLayout lay;
   float b;
   float layer[KF_MAX_LAYERS];

@@ -152,7 +152,9 @@ template <int KIND, bool WIDE>
 struct Lanes {
   LaneRef<WIDE> par, cov, hp, hc, ck;
   int64_t es, n;
-  __device__ __forceinline__ Lanes(int64_t i, int64_t n_, int L, TrackLayout lay) : n(n_) {
+  // L: layers of the hit arrays; Lck: slots of the checkpoint array
+  __device__ __forceinline__ Lanes(int64_t i, int64_t n_, int L, TrackLayout lay, int Lck = -1) : n(n_) {
+    if (Lck < 0) Lck = L;
     using Off = typename LaneRef<WIDE>::Off;
     if (KIND == KF_AOSOA) {
       const int64_t B = int64_t(1) << lay.shift;
@@ -162,7 +164,7 @@ struct Lanes {
       cov.boff = Off((blk * 21 * B + lane) * 4);
       hp.boff = Off((blk * 3 * L * B + lane) * 4);
       hc.boff = Off((blk * 6 * L * B + lane) * 4);
-      ck.boff = Off((blk * 27 * L * B + lane) * 4);
+      ck.boff = Off((blk * 27 * Lck * B + lane) * 4);
     } else if (KIND == KF_AOS) {
       es = 1;
       par.boff = Off(i * 6 * 4);
@@ -179,7 +181,7 @@ struct Lanes {
       cov.bytes = uint32_t(layout_floats(n, 21, 1, lay) * 4);
       hp.bytes = uint32_t(layout_floats(n, 3, L, lay) * 4);
       hc.bytes = uint32_t(layout_floats(n, 6, L, lay) * 4);
-      ck.bytes = uint32_t(layout_floats(n, 27, L, lay) * 4);
+      ck.bytes = uint32_t(layout_floats(n, 27, Lck, lay) * 4);
     }
   }
   // E consecutive elements of one layer (AoS records) from / to array `base`

@@ -59,24 +59,32 @@ struct LaidOutCkpt {
   const StepArgs& a;
   const Lanes<KIND, WIDE>& ln;
   __device__ __forceinline__ void operator()(int k, const float p[6], const float C[21]) const {
-    if (!a.ckpt) return;
+    if (!a.ckpt || (k & ((1 << a.ck_shift) - 1))) return;
     float s[27];
 #pragma unroll
     for (int e = 0; e < 6; ++e) s[e] = p[e];
 #pragma unroll
     for (int e = 0; e < 21; ++e) s[6 + e] = C[e];
-    ln.template st_all<27>(ln.ck, a.ckpt, k, s);
+    ln.template st_all<27>(ln.ck, a.ckpt, k >> a.ck_shift, s);
   }
 };
 
+// Build option: ask the register allocator for at least KF_STEP_MIN_WAVES
+// waves per SIMD (it spills to scratch memory to get there).
+#ifdef KF_STEP_MIN_WAVES
+#define KF_STEP_OCCUPANCY __attribute__((amdgpu_waves_per_eu(KF_STEP_MIN_WAVES, 8)))
+#else
+#define KF_STEP_OCCUPANCY
+#endif
+
 // dynamic LDS: kRingFloats per wave of the block (layouts whose hits are staged)
 template <int GEOM, int PREC, int KIND, bool WIDE>
-__global__ void __launch_bounds__(256) kf_step_kernel(const StepArgs a) {
+__global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const StepArgs a) {
   extern __shared__ float kf_lds[];
   float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kRingFloats;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
+  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.Lck);
   int nl = a.nlay ? a.nlay[i] : a.L;
   nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
   float chi2;

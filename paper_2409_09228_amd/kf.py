@@ -83,7 +83,7 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2409_09228_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
         vp, f32, i32, i64 = ctypes.c_void_p, ctypes.c_float, ctypes.c_int32, ctypes.c_int64
-        step_args = [vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, f32, Layout, ctypes.c_uint32, vp, vp, vp,
+        step_args = [vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, f32, Layout, ctypes.c_uint32, vp, vp, vp, i32,
                      ctypes.POINTER(Tune), vp]
         for name in ("kf_propagate_update_z", "kf_propagate_update_r"):
             fn = getattr(L, name)
@@ -93,10 +93,10 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = [vp, vp, i32, i32, i64, Layout, vp]
             fn.restype = ctypes.c_int
-        L.kf_chi2_backward_z.argtypes = [vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, vp, vp, vp, vp, vp,
+        L.kf_chi2_backward_z.argtypes = [vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, vp, i32, vp, vp, vp, vp,
                                          ctypes.POINTER(Tune), vp]
         L.kf_chi2_backward_z.restype = ctypes.c_int
-        L.kf_checkpoint_floats.argtypes = [i64, i32, Layout]
+        L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
         L.kf_checkpoint_floats.restype = i64
         L.kf_batched_workspace_size.argtypes = [i64]
         L.kf_batched_workspace_size.restype = i64
@@ -167,11 +167,12 @@ def empty_like_layout(n_elem: int, n_layers: int, n: int, layout, device="cuda")
 
 def propagate_update(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n_tracks: int,
                      nlay=None, layout=SOA, flags: int = 0, out=None, chi2=True, status=True,
-                     ckpt=None, tune=None, stream=None):
+                     ckpt=None, ckpt_every: int = 1, tune=None, stream=None):
     """One call of kf_propagate_update_z (geom 0) or _r (geom 1).
 
     Returns (par_out, cov_out, chi2, status).  `out` = (par_out, cov_out) lets
-    the caller pass output buffers (possibly the inputs themselves).
+    the caller pass output buffers (possibly the inputs themselves); `ckpt` (a
+    checkpoint_buffer) receives the state entering every ckpt_every-th layer.
     """
     import torch
     layers = np.ascontiguousarray(layers, np.float32)
@@ -194,7 +195,7 @@ def propagate_update(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n
     with torch.cuda.device(dev):
         rc = fn(_ptr(par), _ptr(cov), _ptr(par_out), _ptr(cov_out), _ptr(hit_pos), _ptr(hit_cov),
                 layers.ctypes.data_as(ctypes.c_void_p), L, _ptr(nlay), int(n_tracks), float(bz),
-                Layout(*layout), int(flags), _ptr(c2), _ptr(st), _ptr(ckpt), tn, _stream(stream))
+                Layout(*layout), int(flags), _ptr(c2), _ptr(st), _ptr(ckpt), int(ckpt_every), tn, _stream(stream))
     _check(rc, "kf_propagate_update_z" if geom == 0 else "kf_propagate_update_r")
     return par_out, cov_out, c2, st
 
@@ -208,7 +209,8 @@ class StepLauncher:
     """
 
     def __init__(self, geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, n_tracks: int,
-                 out, chi2, status, nlay=None, layout=SOA, flags: int = 0, ckpt=None, tune=None, stream=None):
+                 out, chi2, status, nlay=None, layout=SOA, flags: int = 0, ckpt=None, ckpt_every: int = 1,
+                 tune=None, stream=None):
         """Arguments as propagate_update; out = (par_out, cov_out)."""
         import torch
         _require_cuda(par, cov, hit_pos, hit_cov, nlay, ckpt, chi2, status, *out)
@@ -223,7 +225,7 @@ class StepLauncher:
         self._args = (_ptr(par), _ptr(cov), _ptr(out[0]), _ptr(out[1]), _ptr(hit_pos), _ptr(hit_cov),
                       self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]), _ptr(nlay),
                       int(n_tracks), float(bz), Layout(*layout), int(flags), _ptr(chi2), _ptr(status),
-                      _ptr(ckpt), None if self._tune is None else ctypes.byref(self._tune), st)
+                      _ptr(ckpt), int(ckpt_every), None if self._tune is None else ctypes.byref(self._tune), st)
 
     def __call__(self):
         rc = self._fn(*self._args)
@@ -324,11 +326,12 @@ def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
     return out
 
 
-def run_staged(st: dict, flags: int = 0, out=None, ckpt=None, tune=None, stream=None, nlay=True):
+def run_staged(st: dict, flags: int = 0, out=None, ckpt=None, ckpt_every: int = 1, tune=None, stream=None,
+               nlay=True):
     """Filter a staged sample; returns (par_out, cov_out, chi2, status) tensors in its layout."""
     return propagate_update(st["geom"], st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
                             st["bz"], st["n"], nlay=st["nlay"] if nlay else None, layout=st["layout"],
-                            flags=flags, out=out, ckpt=ckpt, tune=tune, stream=stream)
+                            flags=flags, out=out, ckpt=ckpt, ckpt_every=ckpt_every, tune=tune, stream=stream)
 
 
 def results_to_logical(st: dict, par_out, cov_out):
@@ -419,12 +422,16 @@ def release_graphs():
 
 # ----------------------------------------------------------------------------
 # adjoint of the summed chi-square (planes)
-def checkpoint_buffer(n: int, L: int, layout, device="cuda"):
-    """Per-layer entering states for the adjoint: [L][27] per track in `layout`."""
-    return empty_like_layout(27, L, n, layout, device)
+def checkpoint_buffer(n: int, L: int, layout, device="cuda", every: int = 1):
+    """Entering states of layers 0, every, 2 every, ... for the adjoint:
+    [ceil(L / every)][27] per track in `layout`."""
+    if every not in (1, 2, 4, 8, 16, 32, 64):
+        raise ValueError("the checkpoint stride must be a power of two from 1 to 64")
+    return empty_like_layout(27, -(-L // every), n, layout, device)
 
 
-def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None):
+def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,
+                    ckpt_every: int = 1):
     """kf_chi2_backward_z on a staged plane sample; returns (grad_hit_pos, grad_par, grad_cov or None)
     shaped like st["hit_pos"], st["par"], st["cov"]."""
     import torch
@@ -438,7 +445,8 @@ def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune
         rc = lib().kf_chi2_backward_z(_ptr(st["par"]), _ptr(st["cov"]), _ptr(st["hit_pos"]), _ptr(st["hit_cov"]),
                                       layers.ctypes.data_as(ctypes.c_void_p), int(layers.shape[0]), int(st["n"]),
                                       float(st["bz"]), Layout(*st["layout"]), _ptr(status), _ptr(ckpt),
-                                      _ptr(grad_chi2.contiguous()), _ptr(gh), _ptr(gp), _ptr(gc), tn, _stream(stream))
+                                      int(ckpt_every), _ptr(grad_chi2.contiguous()), _ptr(gh), _ptr(gp), _ptr(gc),
+                                      tn, _stream(stream))
     _check(rc, "kf_chi2_backward_z")
     return gh, gp, gc
 
@@ -452,8 +460,9 @@ def _make_autograd():
         forward, kf_chi2_backward_z backward).
 
         apply(par, hit_pos, cov, hit_cov, layer_z, bz, layout, nlay, checkpoint)
-        with tensors in `layout`; checkpoint=True stores the per-layer states
-        in the forward, False recomputes them in the backward.
+        with tensors in `layout`; checkpoint=True (or a stride s) stores the
+        entering state of every (s-th) layer in the forward, False recomputes
+        them in the backward.
         """
 
         @staticmethod
@@ -462,19 +471,22 @@ def _make_autograd():
             if n is None:
                 raise ValueError("KFChi2 takes SoA tensors")
             L = int(np.asarray(layer_z).shape[0])
-            ck = checkpoint_buffer(n, L, layout, par.device) if checkpoint else None
+            every = 1 if checkpoint is True else int(checkpoint)
+            ck = checkpoint_buffer(n, L, layout, par.device, every) if checkpoint else None
             _, _, chi2, status = propagate_update(0, par, cov, hit_pos, hit_cov, layer_z, bz, n, nlay=nlay,
-                                                  layout=layout, ckpt=ck)
+                                                  layout=layout, ckpt=ck, ckpt_every=every)
             ctx.st = {"par": par, "cov": cov, "hit_pos": hit_pos, "hit_cov": hit_cov, "layers": layer_z,
                       "n": n, "bz": bz, "layout": layout}
             ctx.save_for_backward(status)
             ctx.ckpt = ck
+            ctx.every = every
             return chi2
 
         @staticmethod
         def backward(ctx, grad_chi2):
             (status,) = ctx.saved_tensors
-            gh, gp, _ = chi2_backward_z(ctx.st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt)
+            gh, gp, _ = chi2_backward_z(ctx.st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt,
+                                        ckpt_every=ctx.every)
             return gp, gh, None, None, None, None, None, None, None
 
     return KFChi2

@@ -26,7 +26,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_strings():
-    assert K.lib().kf_abi_version() == 2
+    assert K.lib().kf_abi_version() == 3
     assert K.status_string(0) == "ok"
     assert "layout" in K.status_string(3)
 
@@ -38,7 +38,7 @@ def test_array_floats():
     assert K.array_floats(6, 1, 100, (1, 48)) == 0
 
 
-def _call(fn_name, n=10, L=3, layout=K.SOA, flags=0, par=1024, tune=None, ckpt=None):
+def _call(fn_name, n=10, L=3, layout=K.SOA, flags=0, par=1024, tune=None, ckpt=None, every=1):
     lib = K.lib()
     fn = getattr(lib, fn_name)
     layers = (ctypes.c_float * 4)(10, 15, 20, 25)
@@ -46,7 +46,7 @@ def _call(fn_name, n=10, L=3, layout=K.SOA, flags=0, par=1024, tune=None, ckpt=N
     h = ctypes.c_void_p(4096)
     tn = None if tune is None else ctypes.byref(K.Tune(*tune))
     return fn(p, h, h, h, h, h, ctypes.cast(layers, ctypes.c_void_p), L, None, n, 3.8,
-              K.Layout(*layout), flags, None, None, ckpt, tn, None)
+              K.Layout(*layout), flags, None, None, ckpt, every, tn, None)
 
 
 @pytest.mark.parametrize("fn", ["kf_propagate_update_z", "kf_propagate_update_r"])
@@ -64,6 +64,18 @@ def test_argument_validation_before_any_device_call(fn):
     assert _call(fn, n=0) == 0           # nothing to do
     if fn.endswith("_r"):
         assert _call(fn, ckpt=ctypes.c_void_p(8192)) == 9  # KF_E_UNSUPPORTED
+    else:
+        for bad in (3, 6, 128, -2):
+            assert _call(fn, ckpt=ctypes.c_void_p(8192), every=bad) == 2  # stride not a power of two <= 64
+
+
+def test_checkpoint_sizes():
+    lib = K.lib()
+    for every, slots in ((0, 20), (1, 20), (2, 10), (4, 5), (8, 3), (64, 1)):
+        assert lib.kf_checkpoint_floats(100, 20, every, K.Layout(0, 0)) == 100 * 27 * slots
+    assert lib.kf_checkpoint_floats(100, 20, 3, K.Layout(0, 0)) == 0
+    assert lib.kf_checkpoint_floats(100, 20, 4, K.Layout(1, 64)) == 128 * 27 * 5
+    assert tuple(K.checkpoint_buffer(100, 20, K.SOA, "cpu", every=8).shape) == (3, 27, 100)
 
 
 def test_pack_validation():
