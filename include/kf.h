@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 3
+#define KF_ABI_VERSION 4
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -263,6 +263,32 @@ kf_status_t kf_propagate_update_batched(
     int32_t* status_out, void* workspace, int64_t workspace_bytes, const kf_tune_t* tune, void* stream);
 /* Destroy every cached batched-call graph. */
 void kf_batched_release(void);
+
+/*
+ * kf_propagate_update_host -- the step on HOST-resident arrays, transfers
+ * included (the paper times its kernels both with and without the host-device
+ * copies, Sec. 5).  Arguments as kf_propagate_update_z / _r (geometry 0:
+ * planes layer[], 1: cylinders; no checkpoints), but every array pointer is a
+ * HOST pointer -- page-locked memory (hipHostMalloc) lets the copies overlap
+ * the kernels, pageable memory works but serialises them.
+ *
+ * The tracks are cut into chunks of chunk_tracks (0: 131072; rounded up to a
+ * whole AoSoA block); chunk j is copied in, filtered by the same kernels as the
+ * device-resident calls, and copied out on stream j mod n_streams (1 .. 8, 0:
+ * 3), so the copies of one chunk overlap the kernel of another.  The call
+ * returns when every result is in host memory; results are identical to the
+ * device-resident call's.  The library keeps the chunk buffers and streams of
+ * the last configuration per device (about n_streams * chunk_tracks *
+ * (54 + 36 n_layers) * 4 bytes) until kf_host_release.  Not thread-safe
+ * against itself: concurrent calls are serialised.
+ */
+kf_status_t kf_propagate_update_host(
+    int32_t geometry, const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+    const float* hit_pos, const float* hit_cov, const float* layers, int32_t n_layers,
+    const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout, uint32_t flags,
+    float* chi2_out, int32_t* status_out, int64_t chunk_tracks, int32_t n_streams, const kf_tune_t* tune);
+/* Free the host pipeline's device buffers and streams. */
+void kf_host_release(void);
 
 /* Copy between KF_SOA and another layout for an array of n_elem elements per
  * track (n_layers_or_1 = 1 for per-track arrays, the layer count for

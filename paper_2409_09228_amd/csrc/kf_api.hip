@@ -1,5 +1,6 @@
 // C ABI of libkf.so (declared in include/kf.h): argument validation and
-// dispatch to the kernel launchers.  Nothing here allocates device memory.
+// dispatch to the kernel launchers.  Nothing here allocates device memory
+// (the host-resident pipeline's chunk buffers live in kf_host.hip).
 #include <string.h>
 
 #include <list>
@@ -9,6 +10,7 @@
 #include <utility>
 
 #include "kf_batched.h"
+#include "kf_host.h"
 #include "kf_internal.h"
 #include "kf_lanes.h"
 
@@ -235,6 +237,61 @@ int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_ev
   if (n_tracks < 0 || n_layers <= 0 || sh < 0 || !layout_ok(layout, &tl)) return 0;
   return kf::layout_floats(n_tracks, 27, (n_layers + (1 << sh) - 1) >> sh, tl);
 }
+
+kf_status_t kf_propagate_update_host(int32_t geometry, const float* par_in, const float* cov_in, float* par_out,
+                                     float* cov_out, const float* hit_pos, const float* hit_cov, const float* layers,
+                                     int32_t n_layers, const int32_t* n_layers_per_track, int64_t n_tracks,
+                                     float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
+                                     int32_t* status_out, int64_t chunk_tracks, int32_t n_streams,
+                                     const kf_tune_t* tune) {
+  if (geometry != 0 && geometry != 1) return KF_E_SHAPE;
+  if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS || chunk_tracks < 0 || n_streams < 0 ||
+      n_streams > 8)
+    return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  if (flags & ~uint32_t(KF_F_PRECISION)) return KF_E_FLAGS;
+  int block = 256, tpt = 1;
+  if (tune) {
+    block = tune->block_threads;
+    tpt = tune->tracks_per_thread;
+    if ((block != 64 && block != 128 && block != 256) || (tpt != 1 && tpt != 2)) return KF_E_FLAGS;
+  }
+  if (n_tracks == 0) return KF_OK;
+  if (!par_in || !cov_in || !par_out || !cov_out) return KF_E_NULL;
+  if (n_layers > 0 && (!hit_pos || !hit_cov || !layers)) return KF_E_NULL;
+  const void* ptrs[] = {par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, chi2_out, status_out, n_layers_per_track};
+  for (const void* p : ptrs)
+    if (p && !aligned4(p)) return KF_E_ALIGN;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  kf::StepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.L = n_layers;
+  a.lay = tl;
+  a.ck_shift = 0;
+  a.Lck = n_layers;
+  a.b = float(kCLight * double(bz_tesla));
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
+  kf::HostCall h;
+  h.par_in = par_in;
+  h.cov_in = cov_in;
+  h.par_out = par_out;
+  h.cov_out = cov_out;
+  h.hit_pos = hit_pos;
+  h.hit_cov = hit_cov;
+  h.nlay = n_layers_per_track;
+  h.chi2 = chi2_out;
+  h.status = status_out;
+  h.n = n_tracks;
+  h.chunk = chunk_tracks > 0 ? chunk_tracks : (int64_t(1) << 17);
+  h.n_streams = n_streams > 0 ? n_streams : 3;
+  const int prec = (flags & KF_F_JOSEPH) ? 2 : ((flags & KF_F_FP64_INVERSE) ? 1 : 0);
+  const hipError_t e = kf::run_host_pipeline(h, a, geometry, prec, block, tpt);
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
+void kf_host_release(void) { kf::release_host_pipeline(); }
 
 int64_t kf_batched_workspace_size(int64_t n_tracks) {
   return n_tracks < 0 ? 0 : kf::batched_workspace_bytes(n_tracks);

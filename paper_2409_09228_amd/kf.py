@@ -97,6 +97,10 @@ def lib():
                                          ctypes.POINTER(Tune), vp]
         L.kf_chi2_backward_z.restype = ctypes.c_int
         L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
+        L.kf_propagate_update_host.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, f32, Layout,
+                                               ctypes.c_uint32, vp, vp, i64, i32, ctypes.POINTER(Tune)]
+        L.kf_propagate_update_host.restype = ctypes.c_int
+        L.kf_host_release.restype = None
         L.kf_checkpoint_floats.restype = i64
         L.kf_batched_workspace_size.argtypes = [i64]
         L.kf_batched_workspace_size.restype = i64
@@ -324,6 +328,52 @@ def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
         out["hit_pos"] = pack(soa["hit_pos"], 3, L, n, layout)
         out["hit_cov"] = pack(soa["hit_cov"], 6, L, n, layout)
     return out
+
+
+def stage_host(sample: dict, layout=SOA, pinned: bool = True) -> dict:
+    """The sample as host tensors in `layout` -- page-locked (pinned) unless
+    pinned=False -- for propagate_update_host.  (The layout packing itself runs
+    on the GPU, through kf_pack.)"""
+    import torch
+    st = stage_sample(sample, layout)
+    torch.cuda.synchronize()
+    out = dict(st)
+    for k in ("par", "cov", "hit_pos", "hit_cov", "nlay"):
+        t = st[k].cpu()
+        out[k] = t.pin_memory() if pinned else t
+    return out
+
+
+def propagate_update_host(st: dict, flags: int = 0, chunk: int = 0, n_streams: int = 0, tune=None, out=None,
+                          nlay: bool = True):
+    """kf_propagate_update_host on a host-staged sample (stage_host): returns
+    host tensors (par_out, cov_out, chi2, status) in the sample's layout."""
+    import torch
+    for k in ("par", "cov", "hit_pos", "hit_cov"):
+        if st[k].is_cuda:
+            raise ValueError("propagate_update_host takes host tensors")
+    pinned = st["par"].is_pinned()
+    if out is None:
+        par_out = torch.empty_like(st["par"], pin_memory=pinned)
+        cov_out = torch.empty_like(st["cov"], pin_memory=pinned)
+    else:
+        par_out, cov_out = out
+    chi2 = torch.empty(st["n"], dtype=torch.float32, pin_memory=pinned)
+    status = torch.empty(st["n"], dtype=torch.int32, pin_memory=pinned)
+    layers = np.ascontiguousarray(st["layers"], np.float32)
+    tn = None if tune is None else ctypes.byref(make_tune(tune))
+    rc = lib().kf_propagate_update_host(int(st["geom"]), _ptr(st["par"]), _ptr(st["cov"]), _ptr(par_out),
+                                        _ptr(cov_out), _ptr(st["hit_pos"]), _ptr(st["hit_cov"]),
+                                        layers.ctypes.data_as(ctypes.c_void_p), int(layers.shape[0]),
+                                        _ptr(st["nlay"]) if nlay else None, int(st["n"]), float(st["bz"]),
+                                        Layout(*st["layout"]), int(flags), _ptr(chi2), _ptr(status), int(chunk),
+                                        int(n_streams), tn)
+    _check(rc, "kf_propagate_update_host")
+    return par_out, cov_out, chi2, status
+
+
+def release_host():
+    lib().kf_host_release()
 
 
 def run_staged(st: dict, flags: int = 0, out=None, ckpt=None, ckpt_every: int = 1, tune=None, stream=None,

@@ -26,7 +26,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_strings():
-    assert K.lib().kf_abi_version() == 3
+    assert K.lib().kf_abi_version() == 4
     assert K.status_string(0) == "ok"
     assert "layout" in K.status_string(3)
 
