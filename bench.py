@@ -98,9 +98,17 @@ def cpu_baseline(sample, n_tracks: int):
     O.run_sample(sub, nthreads=threads)
     dt = time.perf_counter() - t0
     upd = int(sub["nlay"].sum())
+    # and one thread on a twentieth of that sample
+    one = S.subset(sample, idx[: max(1, len(idx) // 20)])
+    t1 = time.perf_counter()
+    O.run_sample(one, nthreads=1)
+    d1 = time.perf_counter() - t1
+    u1 = int(one["nlay"].sum())
     return {"value": upd / dt, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
             "sample": f"first {len(idx)} tracks ({upd} track-layer updates) of the same sample, "
-                      f"FP64, OpenMP over tracks, {dt:.2f} s wall"}
+                      f"FP64, OpenMP over tracks, {dt:.2f} s wall",
+            "single_thread_value": u1 / d1,
+            "single_thread_sample": f"first {one['par'].shape[0]} tracks ({u1} updates), 1 thread, {d1:.2f} s"}
 
 
 def time_launches(fn, steps: int, stream):

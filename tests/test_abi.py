@@ -84,3 +84,23 @@ def test_pack_validation():
     assert lib.kf_pack(None, None, 6, 1, 10, K.Layout(1, 12), None) == 3
     assert lib.kf_pack(None, None, 6, 1, 10, K.Layout(1, 16), None) == 1
     assert lib.kf_pack(None, None, 6, 1, 0, K.Layout(1, 16), None) == 0
+
+
+def test_host_pipeline_validation_before_any_device_call():
+    lib = K.lib()
+    layers = (ctypes.c_float * 4)(10, 15, 20, 25)
+    h = ctypes.c_void_p(4096)
+
+    def call(geom=0, n=10, L=3, layout=K.SOA, flags=0, chunk=0, streams=0, par=h):
+        return lib.kf_propagate_update_host(geom, par, h, h, h, h, h, ctypes.cast(layers, ctypes.c_void_p), L, None,
+                                            n, 3.8, K.Layout(*layout), flags, None, None, chunk, streams, None)
+    assert call(geom=2) == 2
+    assert call(n=-1) == 2
+    assert call(L=65) == 2
+    assert call(chunk=-5) == 2
+    assert call(streams=9) == 2
+    assert call(layout=(1, 48)) == 3
+    assert call(flags=256) == 8
+    assert call(par=None) == 1
+    assert call(par=ctypes.c_void_p(4098)) == 4
+    assert call(n=0) == 0
