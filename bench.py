@@ -304,6 +304,51 @@ def bench_host(args, sample):
     }
 
 
+def bench_f64(args, sample):
+    """The full-FP64 form (arrays, constants and arithmetic in double) on the
+    same sample, device-resident, timed like the plain form."""
+    import torch
+    from paper_2409_09228_amd import kf as K
+    layout = parse_layout(args.layout)
+    geom = int(sample["geom"][0])
+    n = sample["par"].shape[0]
+    updates = int(sample["nlay"].sum())
+    st = K.stage_sample_f64(sample, layout)
+    stream = torch.cuda.current_stream()
+    launch = K.StepLauncherF64(st, flags=args.flags & 2, tune=(args.block, 1), stream=stream)
+    for _ in range(args.warmup):
+        launch()
+    ms_step = time_launches(launch, args.steps, stream)
+    sec = ms_step / 1e3
+    flops = FLOPS_PER_UPDATE[geom] * updates
+    bytes_ = 2 * (TRACK_BYTES * n + LAYER_BYTES * updates)  # every array in 8-byte words
+    hbm = bytes_ / sec / 1e9
+    tfl = flops / sec / 1e12
+    intensity = flops / bytes_
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(tfl / FP64_PEAK_TFLOPS, 4), "traffic": None}
+    roof.update(intensity_flop_per_byte=round(intensity, 2), ridge_flop_per_byte=round(ridge, 2),
+                alu_achieved_TFLOPs=round(tfl, 3), alu_frac_fp64=round(tfl / FP64_PEAK_TFLOPS, 4),
+                hbm_achieved_GBs=round(hbm, 1), hbm_frac=round(hbm / HBM_PEAK_GBS, 4),
+                hbm_algorithmic_bytes_per_launch=int(bytes_),
+                kernel="kf_step_kernel_f64<%d,%d,%s>" % (geom, 2 if args.flags & 2 else 0, args.layout))
+    ok = int(((launch.status & 0xFF) == 0).sum().item())
+    return {
+        "metric": METRIC + " -- full FP64 form",
+        "value": round(updates / sec, 1), "unit": "track-layer updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "form": "full FP64", "tracks": n, "updates_per_step": updates,
+                   "layout": args.layout, "joseph": bool(args.flags & 2), "block": args.block, "ok_tracks": ok},
+        "roofline": roof,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,9 +365,9 @@ def main(argv=None):
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
                     help="batched form: search the launch shape first and time the winner")
-    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host"],
+    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64"],
                     help="auto: batched for mixed-geometry workloads, plain otherwise; host: host-resident "
-                         "arrays, transfers included")
+                         "arrays, transfers included; f64: the full-FP64 form")
     ap.add_argument("--chunk", type=int, default=0, help="host form: tracks per chunk (0: library default)")
     ap.add_argument("--streams", type=int, default=0, help="host form: HIP streams (0: library default)")
     ap.add_argument("--cpu-tracks", type=int, default=480000)
@@ -359,6 +404,9 @@ def main(argv=None):
         return 0
     if args.form == "host":
         print(json.dumps(bench_host(args, sample)), flush=True)
+        return 0
+    if args.form == "f64":
+        print(json.dumps(bench_f64(args, sample)), flush=True)
         return 0
     if args.form == "batched" or (args.form == "auto" and mixed):
         print(json.dumps(bench_batched(args, sample)), flush=True)

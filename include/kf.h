@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 4
+#define KF_ABI_VERSION 5
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -263,6 +263,26 @@ kf_status_t kf_propagate_update_batched(
     int32_t* status_out, void* workspace, int64_t workspace_bytes, const kf_tune_t* tune, void* stream);
 /* Destroy every cached batched-call graph. */
 void kf_batched_release(void);
+
+/*
+ * kf_propagate_update_z_f64 / kf_propagate_update_r_f64 -- the same steps in
+ * FP64 end to end: double arrays (same layouts, 8-byte elements, 8-byte
+ * aligned), field constant and layer table in double, all arithmetic in
+ * double (the paper's CPU and non-A770 GPU runs; MI355X issues FP64 FMA at
+ * the non-packed FP32 rate).  flags: 0 (plain covariance update) or
+ * KF_F_JOSEPH (Joseph form); KF_F_FP64_INVERSE alone changes nothing here.
+ * Status words and failure handling as the FP32 calls; no checkpoints.
+ */
+kf_status_t kf_propagate_update_z_f64(
+    const double* par_in, const double* cov_in, double* par_out, double* cov_out, const double* hit_pos,
+    const double* hit_cov, const double* layer_z, int32_t n_layers, const int32_t* n_layers_per_track,
+    int64_t n_tracks, double bz_tesla, kf_layout_t layout, uint32_t flags, double* chi2_out, int32_t* status_out,
+    const kf_tune_t* tune, void* stream);
+kf_status_t kf_propagate_update_r_f64(
+    const double* par_in, const double* cov_in, double* par_out, double* cov_out, const double* hit_pos,
+    const double* hit_cov, const double* layer_r, int32_t n_layers, const int32_t* n_layers_per_track,
+    int64_t n_tracks, double bz_tesla, kf_layout_t layout, uint32_t flags, double* chi2_out, int32_t* status_out,
+    const kf_tune_t* tune, void* stream);
 
 /*
  * kf_propagate_update_host -- the step on HOST-resident arrays, transfers

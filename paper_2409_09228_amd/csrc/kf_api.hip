@@ -111,6 +111,51 @@ kf_status_t step(int geom, const float* par_in, const float* cov_in, float* par_
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 
+kf_status_t step_f64(int geom, const double* par_in, const double* cov_in, double* par_out, double* cov_out,
+                     const double* hit_pos, const double* hit_cov, const double* layers, int32_t n_layers,
+                     const int32_t* nlay, int64_t n_tracks, double bz, kf_layout_t layout, uint32_t flags,
+                     double* chi2_out, int32_t* status_out, const kf_tune_t* tune, void* stream) {
+  if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  if (flags & ~uint32_t(KF_F_PRECISION)) return KF_E_FLAGS;
+  int block = 256;
+  if (tune) {
+    block = tune->block_threads;
+    if ((block != 64 && block != 128 && block != 256) || (tune->tracks_per_thread != 1 && tune->tracks_per_thread != 2))
+      return KF_E_FLAGS;
+  }
+  if (n_tracks == 0) return KF_OK;
+  if (!par_in || !cov_in || !par_out || !cov_out) return KF_E_NULL;
+  if (n_layers > 0 && (!hit_pos || !hit_cov || !layers)) return KF_E_NULL;
+  const void* ptrs8[] = {par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, chi2_out};
+  for (const void* p : ptrs8)
+    if (p && (reinterpret_cast<uintptr_t>(p) & 7u)) return KF_E_ALIGN;
+  if ((status_out && !aligned4(status_out)) || (nlay && !aligned4(nlay))) return KF_E_ALIGN;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  kf::StepArgsT<double> a;
+  memset(&a, 0, sizeof(a));
+  a.par_in = par_in;
+  a.cov_in = cov_in;
+  a.par_out = par_out;
+  a.cov_out = cov_out;
+  a.hit_pos = hit_pos;
+  a.hit_cov = hit_cov;
+  a.nlay = nlay;
+  a.chi2 = chi2_out;
+  a.status = status_out;
+  a.n = n_tracks;
+  a.L = n_layers;
+  a.Lck = n_layers;
+  a.lay = tl;
+  a.b = kCLight * bz;
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0;
+  const int prec = (flags & KF_F_JOSEPH) ? 2 : 0;
+  hipError_t e = kf::launch_step_f64(geom, prec, block, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
 kf_status_t pack_common(const float* src, float* dst, int32_t n_elem, int32_t n_layers, int64_t n,
                         kf_layout_t layout, void* stream, bool to_layout) {
   if (n_elem <= 0 || n_layers <= 0 || n < 0) return KF_E_SHAPE;
@@ -236,6 +281,24 @@ int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_ev
   const int sh = ckpt_shift(ckpt_every);
   if (n_tracks < 0 || n_layers <= 0 || sh < 0 || !layout_ok(layout, &tl)) return 0;
   return kf::layout_floats(n_tracks, 27, (n_layers + (1 << sh) - 1) >> sh, tl);
+}
+
+kf_status_t kf_propagate_update_z_f64(const double* par_in, const double* cov_in, double* par_out, double* cov_out,
+                                      const double* hit_pos, const double* hit_cov, const double* layer_z,
+                                      int32_t n_layers, const int32_t* n_layers_per_track, int64_t n_tracks,
+                                      double bz_tesla, kf_layout_t layout, uint32_t flags, double* chi2_out,
+                                      int32_t* status_out, const kf_tune_t* tune, void* stream) {
+  return step_f64(0, par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, layer_z, n_layers, n_layers_per_track,
+                  n_tracks, bz_tesla, layout, flags, chi2_out, status_out, tune, stream);
+}
+
+kf_status_t kf_propagate_update_r_f64(const double* par_in, const double* cov_in, double* par_out, double* cov_out,
+                                      const double* hit_pos, const double* hit_cov, const double* layer_r,
+                                      int32_t n_layers, const int32_t* n_layers_per_track, int64_t n_tracks,
+                                      double bz_tesla, kf_layout_t layout, uint32_t flags, double* chi2_out,
+                                      int32_t* status_out, const kf_tune_t* tune, void* stream) {
+  return step_f64(1, par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, layer_r, n_layers, n_layers_per_track,
+                  n_tracks, bz_tesla, layout, flags, chi2_out, status_out, tune, stream);
 }
 
 kf_status_t kf_propagate_update_host(int32_t geometry, const float* par_in, const float* cov_in, float* par_out,

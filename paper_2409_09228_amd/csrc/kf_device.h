@@ -123,9 +123,11 @@ __device__ __forceinline__ void helix_trig(float u, float& su, float& cu, float&
 // < 1e-10) and cos d = 1 - d^2/2 + d^4/24 - d^6/720 (< 2e-12); a larger step
 // (a poor seed) re-evaluates sin and cos of the updated angle itself.  The
 // rounding of the carried pair drifts by about one ulp per layer.
-struct Dir {
-  float sp, cp, st, ct;  // sin phi, cos phi, sin theta, cos theta
+template <class T>
+struct DirT {
+  T sp, cp, st, ct;  // sin phi, cos phi, sin theta, cos theta
 };
+using Dir = DirT<float>;
 
 __device__ __forceinline__ void dir_init(const float p[6], Dir& d) {
   sincos_r(p[4], &d.sp, &d.cp);
@@ -155,6 +157,45 @@ __device__ __forceinline__ void sinc_g_t(float u, float su, float cu, float& sin
 __device__ __forceinline__ void helix_trig_t(float u, float& su, float& cu, float& sinc, float& g) {
   helix_trig<true>(u, su, cu, sinc, g);
 }
+__device__ __forceinline__ void helix_sinc_t(float u, float& su, float& cu, float& sinc) {
+  float unused;
+  helix_trig<false>(u, su, cu, sinc, unused);
+}
+__device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
+__device__ __forceinline__ float fmax_t(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ float fabs_t(float x) { return fabsf(x); }
+
+// The same helpers in FP64 (the full-FP64 form of the step).  sin and cos are
+// the library's; the division is exact IEEE division.  sinc u and G(u) use
+// their Taylor series for |u| < 1/10 -- through u^10, truncation below 1e-22
+// relative -- and the closed forms beyond, where the cancellation in
+// sin u - u cos u (about u^3/3) costs at most 7e-14 relative.  The direction
+// cosines are not carried across layers in FP64: a changed angle is
+// re-evaluated (rotate_by).
+__device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
+__device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
+__device__ __forceinline__ double fmax_t(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double fabs_t(double x) { return fabs(x); }
+__device__ __forceinline__ void helix_sinc_t(double u, double& su, double& cu, double& sinc) {
+  sincos(u, &su, &cu);
+  const double u2 = u * u;
+  const double ss =
+      1.0 + u2 * (-1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (-1.0 / 5040.0 + u2 * (1.0 / 362880.0 + u2 * (-1.0 / 39916800.0)))));
+  sinc = fabs(u) < 0.1 ? ss : su / u;
+}
+__device__ __forceinline__ void helix_trig_t(double u, double& su, double& cu, double& sinc, double& g) {
+  helix_sinc_t(u, su, cu, sinc);
+  const double u2 = u * u;
+  const double gs = u * (1.0 / 3.0 + u2 * (-1.0 / 30.0 + u2 * (1.0 / 840.0 + u2 * (-1.0 / 45360.0 + u2 * (1.0 / 3991680.0 +
+                                                                                       u2 * (-1.0 / 518918400.0))))));
+  g = fabs(u) < 0.1 ? gs : (su - u * cu) / u2;
+}
+__device__ __forceinline__ void dir_init(const double p[6], DirT<double>& d) {
+  sincos(p[4], &d.sp, &d.cp);
+  sincos(p[5], &d.st, &d.ct);
+}
+__device__ __forceinline__ void rotate_by(double& s, double& c, double, double angle) { sincos(angle, &s, &c); }
 
 // The non-trivial entries of the plane Jacobian F:
 //   row x   = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th
@@ -180,9 +221,11 @@ struct PlaneJac {
 // dp/ds = (cos phi', sin phi', cot theta, 0, omega, 0) and
 // grad s = (0, 0, -tan theta, 0, 0, (zk - z)/cos^2 theta).  The z row of F is
 // identically zero, so the z row and column of the transported covariance vanish.
-template <class T>
+// T: the state's scalar (float, double, or dual numbers); S: the geometry's
+// (layer position and field constant: float, or double in the FP64 form).
+template <class T, class S>
 __device__ __forceinline__ void helix_to_plane_dir(const T p[6], const T& sth, const T& cth, const T& sp, const T& cp,
-                                                   float zk, float b, T q[6], PlaneJac<T>& J, T& sP, T& cP) {
+                                                   S zk, S b, T q[6], PlaneJac<T>& J, T& sP, T& cP) {
   const T rcth = rcp_t(cth);
   const T tanth = sth * rcth;
   const T dz = zk - p[2];
@@ -223,37 +266,37 @@ __device__ __forceinline__ void helix_to_plane_dir(const T p[6], const T& sth, c
 }
 
 // The same, evaluating the direction's sin and cos from p itself.
-template <class T>
-__device__ __forceinline__ void helix_to_plane(const T p[6], float zk, float b, T q[6], PlaneJac<T>& J) {
+template <class T, class S>
+__device__ __forceinline__ void helix_to_plane(const T p[6], S zk, S b, T q[6], PlaneJac<T>& J) {
   T sth, cth, sp, cp, sP, cP;
   sincos_t(p[5], &sth, &cth);
   sincos_t(p[4], &sp, &cp);
-  helix_to_plane_dir<T>(p, sth, cth, sp, cp, zk, b, q, J, sP, cP);
+  helix_to_plane_dir<T, S>(p, sth, cth, sp, cp, zk, b, q, J, sP, cP);
 }
 
 // Pt = F C F^T for the plane Jacobian, on packed covariances.  ZIN: the z row
 // and column of C are known to be zero (C is the result of a plane update),
 // which removes the z column from every product.
-template <bool ZIN>
-__device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const float C[21], float Pt[21]) {
-  const float a0 = J.a0, a1 = J.a1, a2 = J.a2, a3 = J.a3;
-  const float b0 = J.b0, b1 = J.b1, b2 = J.b2, b3 = J.b3;
-  const float c0 = J.c0, c1 = J.c1, c3 = J.c3;
+template <bool ZIN, class T>
+__device__ __forceinline__ void transport_plane(const PlaneJac<T>& J, const T C[21], T Pt[21]) {
+  const T a0 = J.a0, a1 = J.a1, a2 = J.a2, a3 = J.a3;
+  const T b0 = J.b0, b1 = J.b1, b2 = J.b2, b3 = J.b3;
+  const T c0 = J.c0, c1 = J.c1, c3 = J.c3;
   // W_r = C F_r^T (column r of C F^T) for the three non-trivial rows
-  float Wx[6], Wy[6], Wf[6];
+  T Wx[6], Wy[6], Wf[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float c3_ = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
+    const T c3_ = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
     if (ZIN) {
       if (i == 2) {
-        Wx[i] = Wy[i] = Wf[i] = 0.0f;
+        Wx[i] = Wy[i] = Wf[i] = T(0);
         continue;
       }
       Wx[i] = C[ix(i, 0)] + a1 * c3_ + a2 * c4 + a3 * c5;
       Wy[i] = C[ix(i, 1)] + b1 * c3_ + b2 * c4 + b3 * c5;
       Wf[i] = c1 * c3_ + c4 + c3 * c5;
     } else {
-      const float c2 = C[ix(i, 2)];
+      const T c2 = C[ix(i, 2)];
       Wx[i] = C[ix(i, 0)] + a0 * c2 + a1 * c3_ + a2 * c4 + a3 * c5;
       Wy[i] = C[ix(i, 1)] + b0 * c2 + b1 * c3_ + b2 * c4 + b3 * c5;
       Wf[i] = c0 * c2 + c1 * c3_ + c4 + c3 * c5;
@@ -276,28 +319,27 @@ __device__ __forceinline__ void transport_plane(const PlaneJac<float>& J, const 
     Pt[ix(4, 3)] = c0 * C[ix(2, 3)] + c1 * C[ix(3, 3)] + C[ix(4, 3)] + c3 * C[ix(5, 3)];
     Pt[ix(4, 4)] = c0 * Wf[2] + c1 * Wf[3] + Wf[4] + c3 * Wf[5];
   }
-  Pt[ix(2, 0)] = 0.0f;
-  Pt[ix(2, 1)] = 0.0f;
-  Pt[ix(2, 2)] = 0.0f;
+  Pt[ix(2, 0)] = T(0);
+  Pt[ix(2, 1)] = T(0);
+  Pt[ix(2, 2)] = T(0);
   Pt[ix(3, 0)] = Wx[3];
   Pt[ix(3, 1)] = Wy[3];
-  Pt[ix(3, 2)] = 0.0f;
+  Pt[ix(3, 2)] = T(0);
   Pt[ix(3, 3)] = C[ix(3, 3)];
-  Pt[ix(4, 2)] = 0.0f;
+  Pt[ix(4, 2)] = T(0);
   Pt[ix(5, 0)] = Wx[5];
   Pt[ix(5, 1)] = Wy[5];
-  Pt[ix(5, 2)] = 0.0f;
+  Pt[ix(5, 2)] = T(0);
   Pt[ix(5, 3)] = C[ix(5, 3)];
   Pt[ix(5, 4)] = Wf[5];
   Pt[ix(5, 5)] = C[ix(5, 5)];
 }
 
 // d: sin and cos of the direction angles of p on entry, of q on return.
-template <bool ZIN>
-__device__ __forceinline__ void propagate_z(const float p[6], const float C[21], Dir& d, float zk, float b,
-                                            float q[6], float Pt[21]) {
-  PlaneJac<float> J;
-  helix_to_plane_dir<float>(p, d.st, d.ct, d.sp, d.cp, zk, b, q, J, d.sp, d.cp);
+template <bool ZIN, class T>
+__device__ __forceinline__ void propagate_z(const T p[6], const T C[21], DirT<T>& d, T zk, T b, T q[6], T Pt[21]) {
+  PlaneJac<T> J;
+  helix_to_plane_dir<T, T>(p, d.st, d.ct, d.sp, d.cp, zk, b, q, J, d.sp, d.cp);
   transport_plane<ZIN>(J, C, Pt);
 }
 
@@ -316,48 +358,48 @@ __device__ __forceinline__ void propagate_z(const float p[6], const float C[21],
 // Returns status bits (0 on success): an unreachable cylinder first, then a
 // crossing the iteration did not land on.  d: sin and cos of the direction
 // angles of p on entry, of q on return.
-__device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[21], Dir& d, float rk, float b,
-                                                float q[6], float Pt[21]) {
-  const float sth = d.st, cth = d.ct, sp = d.sp, cp = d.cp;
-  const float om = -b * p[3];
-  const float x = p[0], y = p[1];
-  const float rho2 = x * x + y * y;
-  const float rk2 = rk * rk;
-  const float reach = 0.5f * om * (rk2 - rho2) + (x * sp - y * cp);
-  const bool reachable = fabsf(reach) <= rk;
-  const float beta = x * cp + y * sp;
-  float s = -beta + sqrtf(fmaxf(beta * beta - rho2 + rk2, 0.0f));
+template <class T>
+__device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], DirT<T>& d, T rk, T b, T q[6], T Pt[21]) {
+  const T sth = d.st, cth = d.ct, sp = d.sp, cp = d.cp;
+  const T om = -b * p[3];
+  const T x = p[0], y = p[1];
+  const T rho2 = x * x + y * y;
+  const T rk2 = rk * rk;
+  const T reach = 0.5f * om * (rk2 - rho2) + (x * sp - y * cp);
+  const bool reachable = fabs_t(reach) <= rk;
+  const T beta = x * cp + y * sp;
+  T s = -beta + sqrt_t(fmax_t(beta * beta - rho2 + rk2, T(0)));
 #pragma unroll
   for (int it = 0; it < 5; ++it) {
-    const float u = 0.5f * om * s;
-    float su, cu, sinc, unused;
-    helix_trig<false>(u, su, cu, sinc, unused);
-    const float cA = cp * cu - sp * su;
-    const float sA = sp * cu + cp * su;
-    const float ch = s * sinc;
-    const float X = x + ch * cA;
-    const float Y = y + ch * sA;
-    const float cP = cA * cu - sA * su;
-    const float sP = sA * cu + cA * su;
-    const float gg = X * X + Y * Y - rk2;
-    const float gp = 2.0f * (X * cP + Y * sP);
-    s = s - gg * rcp(gp);
+    const T u = 0.5f * om * s;
+    T su, cu, sinc;
+    helix_sinc_t(u, su, cu, sinc);
+    const T cA = cp * cu - sp * su;
+    const T sA = sp * cu + cp * su;
+    const T ch = s * sinc;
+    const T X = x + ch * cA;
+    const T Y = y + ch * sA;
+    const T cP = cA * cu - sA * su;
+    const T sP = sA * cu + cA * su;
+    const T gg = X * X + Y * Y - rk2;
+    const T gp = 2.0f * (X * cP + Y * sP);
+    s = s - gg * rcp_t(gp);
   }
-  const float u = 0.5f * om * s;
-  float su, cu, sinc, g;
-  helix_trig<true>(u, su, cu, sinc, g);
-  const float cA = cp * cu - sp * su;
-  const float sA = sp * cu + cp * su;
-  const float ch = s * sinc;
-  const float dx = ch * cA, dy = ch * sA;
-  const float X = x + dx, Y = y + dy;
-  const float cP = cA * cu - sA * su;
-  const float sP = sA * cu + cA * su;
+  const T u = 0.5f * om * s;
+  T su, cu, sinc, g;
+  helix_trig_t(u, su, cu, sinc, g);
+  const T cA = cp * cu - sp * su;
+  const T sA = sp * cu + cp * su;
+  const T ch = s * sinc;
+  const T dx = ch * cA, dy = ch * sA;
+  const T X = x + dx, Y = y + dy;
+  const T cP = cA * cu - sA * su;
+  const T sP = sA * cu + cA * su;
   d.cp = cP;
   d.sp = sP;
-  const bool on_surface = fabsf(X * X + Y * Y - rk2) <= 2.0e-4f * rk2;
-  const float rsth = rcp(sth);
-  const float cot = cth * rsth;
+  const bool on_surface = fabs_t(X * X + Y * Y - rk2) <= T(2.0e-4f) * rk2;
+  const T rsth = rcp_t(sth);
+  const T cot = cth * rsth;
   q[0] = X;
   q[1] = Y;
   q[2] = p[2] + s * cot;
@@ -365,26 +407,26 @@ __device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[
   q[4] = p[4] + om * s;
   q[5] = p[5];
 
-  const float hs2 = 0.5f * s * s;
-  const float Jxk = b * hs2 * (sA * sinc + cA * g);   // -b d dx/d omega
-  const float Jyk = -b * hs2 * (cA * sinc - sA * g);  // -b d dy/d omega
-  const float Jxf = -dy, Jyf = dx;
-  const float Jzt = -s * rsth * rsth;
-  const float Jfk = -b * s;
-  const float rD = rcp(X * cP + Y * sP);
-  const float dsx = -X * rD, dsy = -Y * rD;
-  const float dsk = -(X * Jxk + Y * Jyk) * rD;
-  const float dsf = -(X * Jxf + Y * Jyf) * rD;
+  const T hs2 = 0.5f * s * s;
+  const T Jxk = b * hs2 * (sA * sinc + cA * g);   // -b d dx/d omega
+  const T Jyk = -b * hs2 * (cA * sinc - sA * g);  // -b d dy/d omega
+  const T Jxf = -dy, Jyf = dx;
+  const T Jzt = -s * rsth * rsth;
+  const T Jfk = -b * s;
+  const T rD = rcp_t(X * cP + Y * sP);
+  const T dsx = -X * rD, dsy = -Y * rD;
+  const T dsk = -(X * Jxk + Y * Jyk) * rD;
+  const T dsf = -(X * Jxf + Y * Jyf) * rD;
   // F rows x, y, phi live in columns (x, y, kappa, phi); row z in all six.
-  const float Fx0 = 1.0f + cP * dsx, Fx1 = cP * dsy, Fx3 = Jxk + cP * dsk, Fx4 = Jxf + cP * dsf;
-  const float Fy0 = sP * dsx, Fy1 = 1.0f + sP * dsy, Fy3 = Jyk + sP * dsk, Fy4 = Jyf + sP * dsf;
-  const float Fz0 = cot * dsx, Fz1 = cot * dsy, Fz3 = cot * dsk, Fz4 = cot * dsf, Fz5 = Jzt;
-  const float Ff0 = om * dsx, Ff1 = om * dsy, Ff3 = Jfk + om * dsk, Ff4 = 1.0f + om * dsf;
+  const T Fx0 = 1.0f + cP * dsx, Fx1 = cP * dsy, Fx3 = Jxk + cP * dsk, Fx4 = Jxf + cP * dsf;
+  const T Fy0 = sP * dsx, Fy1 = 1.0f + sP * dsy, Fy3 = Jyk + sP * dsk, Fy4 = Jyf + sP * dsf;
+  const T Fz0 = cot * dsx, Fz1 = cot * dsy, Fz3 = cot * dsk, Fz4 = cot * dsf, Fz5 = Jzt;
+  const T Ff0 = om * dsx, Ff1 = om * dsy, Ff3 = Jfk + om * dsk, Ff4 = 1.0f + om * dsf;
 
-  float Wx[6], Wy[6], Wz[6], Wf[6];
+  T Wx[6], Wy[6], Wz[6], Wf[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const float c0 = C[ix(i, 0)], c1 = C[ix(i, 1)], c2 = C[ix(i, 2)], c3 = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
+    const T c0 = C[ix(i, 0)], c1 = C[ix(i, 1)], c2 = C[ix(i, 2)], c3 = C[ix(i, 3)], c4 = C[ix(i, 4)], c5 = C[ix(i, 5)];
     Wx[i] = Fx0 * c0 + Fx1 * c1 + Fx3 * c3 + Fx4 * c4;
     Wy[i] = Fy0 * c0 + Fy1 * c1 + Fy3 * c3 + Fy4 * c4;
     Wz[i] = Fz0 * c0 + Fz1 * c1 + c2 + Fz3 * c3 + Fz4 * c4 + Fz5 * c5;
@@ -426,60 +468,59 @@ __device__ __forceinline__ uint32_t propagate_r(const float p[6], const float C[
 // updated values and the returned status bits (0 on success) say whether they
 // may be used.  The checks come in a fixed order: non-finite r or S, then S
 // not positive definite, then a non-finite result.
-template <bool ZROW>
-__device__ __forceinline__ uint32_t update_f32(float q[6], float Pt[21], const float m[3], const float V[6],
-                                               float& dchi) {
-  const float r0 = m[0] - q[0], r1 = m[1] - q[1], r2 = m[2] - q[2];
-  const float S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
-  const float S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
+template <bool ZROW, class T>
+__device__ __forceinline__ uint32_t update_f32(T q[6], T Pt[21], const T m[3], const T V[6], T& dchi) {
+  const T r0 = m[0] - q[0], r1 = m[1] - q[1], r2 = m[2] - q[2];
+  const T S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
+  const T S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
   const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
-  const float c00 = S11 * S22 - S21 * S21;
-  const float c10 = S20 * S21 - S10 * S22;
-  const float c11 = S00 * S22 - S20 * S20;
-  const float c20 = S10 * S21 - S11 * S20;
-  const float c21 = S10 * S20 - S00 * S21;
-  const float c22 = S00 * S11 - S10 * S10;
-  const float det = S00 * c00 + S10 * c10 + S20 * c20;
+  const T c00 = S11 * S22 - S21 * S21;
+  const T c10 = S20 * S21 - S10 * S22;
+  const T c11 = S00 * S22 - S20 * S20;
+  const T c20 = S10 * S21 - S11 * S20;
+  const T c21 = S10 * S20 - S00 * S21;
+  const T c22 = S00 * S11 - S10 * S10;
+  const T det = S00 * c00 + S10 * c10 + S20 * c20;
   const bool pd = (S00 > 0.0f) & (c22 > 0.0f) & (det > 0.0f);
-  const float rdet = rcp(det);
-  const float i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
-  const float i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
+  const T rdet = rcp_t(det);
+  const T i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
+  const T i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
   // t = S^-1 r
-  const float t0 = i00 * r0 + i10 * r1 + i20 * r2;
-  const float t1 = i10 * r0 + i11 * r1 + i21 * r2;
-  const float t2 = i20 * r0 + i21 * r1 + i22 * r2;
+  const T t0 = i00 * r0 + i10 * r1 + i20 * r2;
+  const T t1 = i10 * r0 + i11 * r1 + i21 * r2;
+  const T t2 = i20 * r0 + i21 * r1 + i22 * r2;
   dchi = r0 * t0 + r1 * t1 + r2 * t2;
   if (ZROW) {
     // row/column 2 of Pt vanish: K_i = Pt_i0 S^-1_0: + Pt_i1 S^-1_1:
-    float K0[6], K1[6];
+    T K0[6], K1[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       if (i == 2) continue;
-      const float a = Pt[ix(i, 0)], c = Pt[ix(i, 1)];
+      const T a = Pt[ix(i, 0)], c = Pt[ix(i, 1)];
       K0[i] = a * i00 + c * i10;
       K1[i] = a * i10 + c * i11;
     }
-    float Pn[21];
+    T Pn[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = 0; j <= i; ++j)
-        Pn[ix(i, j)] = (i == 2 || j == 2) ? 0.0f : Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)];
+        Pn[ix(i, j)] = (i == 2 || j == 2) ? T(0) : Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
       if (i != 2) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1;
 #pragma unroll
     for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
   } else {
-    float K0[6], K1[6], K2[6];
+    T K0[6], K1[6], K2[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
-      const float a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
+      const T a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
       K0[i] = a * i00 + c * i10 + d * i20;
       K1[i] = a * i10 + c * i11 + d * i21;
       K2[i] = a * i20 + c * i21 + d * i22;
     }
-    float Pn[21];
+    T Pn[21];
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -500,9 +541,8 @@ __device__ __forceinline__ uint32_t update_f32(float q[6], float Pt[21], const f
 // covariance update in FP64 too, in plain form or, with JOSEPH, as
 //   P' = (I - K H) Pt (I - K H)^T + K V K^T
 // (symmetric and positive semi-definite by construction).  Bulk state stays FP32.
-template <bool JOSEPH>
-__device__ __forceinline__ uint32_t update_f64(float q[6], float Pt[21], const float m[3], const float V[6],
-                                               float& dchi) {
+template <bool JOSEPH, class T>
+__device__ __forceinline__ uint32_t update_f64(T q[6], T Pt[21], const T m[3], const T V[6], T& dchi) {
   const double r0 = (double)m[0] - (double)q[0], r1 = (double)m[1] - (double)q[1], r2 = (double)m[2] - (double)q[2];
   const double S00 = (double)Pt[0] + V[0], S10 = (double)Pt[1] + V[1], S11 = (double)Pt[2] + V[2];
   const double S20 = (double)Pt[3] + V[3], S21 = (double)Pt[4] + V[4], S22 = (double)Pt[5] + V[5];
@@ -523,21 +563,21 @@ __device__ __forceinline__ uint32_t update_f64(float q[6], float Pt[21], const f
   const double t2 = i20 * r0 + i21 * r1 + i22 * r2;
   const double chi = r0 * t0 + r1 * t1 + r2 * t2;
   double K0[6], K1[6], K2[6];
-  float qn[6], Pn[21];
+  T qn[6], Pn[21];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     const double a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
     K0[i] = a * i00 + c * i10 + d * i20;
     K1[i] = a * i10 + c * i11 + d * i21;
     K2[i] = a * i20 + c * i21 + d * i22;
-    qn[i] = (float)((double)q[i] + a * t0 + c * t1 + d * t2);
+    qn[i] = (T)((double)q[i] + a * t0 + c * t1 + d * t2);
   }
   if (!JOSEPH) {
 #pragma unroll
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = 0; j <= i; ++j)
-        Pn[ix(i, j)] = (float)((double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] -
+        Pn[ix(i, j)] = (T)((double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] -
                                K1[i] * (double)Pt[ix(1, j)] - K2[i] * (double)Pt[ix(2, j)]);
   } else {
     const double v00 = V[0], v10 = V[1], v11 = V[2], v20 = V[3], v21 = V[4], v22 = V[5];
@@ -553,10 +593,10 @@ __device__ __forceinline__ uint32_t update_f64(float q[6], float Pt[21], const f
       const double e1 = M[1] - (K0[i] * v10 + K1[i] * v11 + K2[i] * v21);
       const double e2 = M[2] - (K0[i] * v20 + K1[i] * v21 + K2[i] * v22);
 #pragma unroll
-      for (int j = 0; j <= i; ++j) Pn[ix(i, j)] = (float)(M[j] - e0 * K0[j] - e1 * K1[j] - e2 * K2[j]);
+      for (int j = 0; j <= i; ++j) Pn[ix(i, j)] = (T)(M[j] - e0 * K0[j] - e1 * K1[j] - e2 * K2[j]);
     }
   }
-  dchi = (float)chi;
+  dchi = (T)chi;
   bool out_ok = fin(dchi);
 #pragma unroll
   for (int i = 0; i < 6; ++i) out_ok = out_ok & fin(qn[i]) & fin(Pn[ix(i, i)]);
@@ -570,22 +610,22 @@ __device__ __forceinline__ uint32_t update_f64(float q[6], float Pt[21], const f
 // precision variants of the update
 enum { PREC_F32 = 0, PREC_F64 = 1, PREC_F64_JOSEPH = 2 };
 
-template <int GEOM, int PREC>
-__device__ __forceinline__ uint32_t update(float q[6], float Pt[21], const float m[3], const float V[6], float& dchi) {
-  if (PREC == PREC_F32) return update_f32<GEOM == 0>(q, Pt, m, V, dchi);
-  if (PREC == PREC_F64) return update_f64<false>(q, Pt, m, V, dchi);
-  return update_f64<true>(q, Pt, m, V, dchi);
+template <int GEOM, int PREC, class T>
+__device__ __forceinline__ uint32_t update(T q[6], T Pt[21], const T m[3], const T V[6], T& dchi) {
+  if (PREC == PREC_F32) return update_f32<GEOM == 0, T>(q, Pt, m, V, dchi);
+  if (PREC == PREC_F64) return update_f64<false, T>(q, Pt, m, V, dchi);
+  return update_f64<true, T>(q, Pt, m, V, dchi);
 }
 
 // ZIN (planes): C has the zero z row and column a plane update leaves.
-template <int GEOM, bool ZIN>
-__device__ __forceinline__ uint32_t propagate(const float p[6], const float C[21], Dir& d, float target, float b,
-                                              float q[6], float Pt[21]) {
+template <int GEOM, bool ZIN, class T>
+__device__ __forceinline__ uint32_t propagate(const T p[6], const T C[21], DirT<T>& d, T target, T b, T q[6],
+                                              T Pt[21]) {
   if (GEOM == 0) {
-    propagate_z<ZIN>(p, C, d, target, b, q, Pt);
+    propagate_z<ZIN, T>(p, C, d, target, b, q, Pt);
     return 0u;
   }
-  return propagate_r(p, C, d, target, b, q, Pt);
+  return propagate_r<T>(p, C, d, target, b, q, Pt);
 }
 
 }  // namespace kf

@@ -15,25 +15,30 @@ struct TrackLayout {
   int32_t shift; // log2(B) for AoSoA
 };
 
-struct StepArgs {
-  const float* par_in;
-  const float* cov_in;
-  float* par_out;
-  float* cov_out;
-  const float* hit_pos;
-  const float* hit_cov;
+// One plain step call; T is the scalar of every array, of the field constant
+// and of the layer table (float, or double in the FP64 form).
+template <class T>
+struct StepArgsT {
+  using Scalar = T;
+  const T* par_in;
+  const T* cov_in;
+  T* par_out;
+  T* cov_out;
+  const T* hit_pos;
+  const T* hit_cov;
   const int32_t* nlay;
-  float* chi2;
+  T* chi2;
   int32_t* status;
-  float* ckpt;
+  T* ckpt;
   int64_t n;
   int32_t L;
   int32_t ck_shift;  // log2 of the checkpoint stride
   int32_t Lck;       // checkpoint slots per track: ceil(L / stride)
   TrackLayout lay;
-  float b;  // 0.00299792458 * Bz
-  float layer[KF_MAX_LAYERS];
+  T b;  // 0.00299792458 * Bz
+  T layer[KF_MAX_LAYERS];
 };
+using StepArgs = StepArgsT<float>;
 
 struct AdjointArgs {
   const float* par_in;
@@ -59,6 +64,9 @@ hipError_t launch_adjoint_z(int block, const AdjointArgs& a, hipStream_t s);
 
 // precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
 hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);
+// The FP64 form: FP64 arrays, FP64 arithmetic throughout (prec 0 plain update,
+// 2 Joseph update)
+hipError_t launch_step_f64(int geom, int prec, int block, const StepArgsT<double>& a, hipStream_t s);
 
 hipError_t launch_pack(const float* src, float* dst, int32_t E, int32_t L, int64_t n, TrackLayout lay,
                        bool to_layout, hipStream_t s);

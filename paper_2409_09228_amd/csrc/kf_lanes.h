@@ -46,20 +46,20 @@ inline bool needs_wide(int64_t n, int L, TrackLayout lay) {
 
 // N consecutive floats (4-byte aligned) as one record: the compiler emits
 // multi-dword loads/stores (dwordx2/x3/x4) instead of N dword accesses.
-template <int N>
+template <int N, class T = float>
 struct __attribute__((packed, aligned(4))) FRec {
-  float v[N];
+  T v[N];
 };
-template <int N>
-__device__ __forceinline__ void ld_rec(const float* p, float* dst) {
-  FRec<N> r;
+template <int N, class T>
+__device__ __forceinline__ void ld_rec(const T* p, T* dst) {
+  FRec<N, T> r;
   __builtin_memcpy(&r, p, sizeof(r));
 #pragma unroll
   for (int i = 0; i < N; ++i) dst[i] = r.v[i];
 }
-template <int N>
-__device__ __forceinline__ void st_rec(float* p, const float* src) {
-  FRec<N> r;
+template <int N, class T>
+__device__ __forceinline__ void st_rec(T* p, const T* src) {
+  FRec<N, T> r;
 #pragma unroll
   for (int i = 0; i < N; ++i) r.v[i] = src[i];
   __builtin_memcpy(p, &r, sizeof(r));
@@ -140,16 +140,21 @@ struct LaneRef {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   Off boff;        // byte offset of this lane's element 0, layer 0
   uint32_t bytes;  // size of the array (buffer form)
-  __device__ __forceinline__ const float* at(const float* base, int64_t uni) const {
-    return reinterpret_cast<const float*>(reinterpret_cast<const char*>(base + uni) + boff);
+  template <class T>
+  __device__ __forceinline__ const T* at(const T* base, int64_t uni) const {
+    return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base + uni) + boff);
   }
-  __device__ __forceinline__ float* at(float* base, int64_t uni) const {
-    return reinterpret_cast<float*>(reinterpret_cast<char*>(base + uni) + boff);
+  template <class T>
+  __device__ __forceinline__ T* at(T* base, int64_t uni) const {
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base + uni) + boff);
   }
 };
 
-template <int KIND, bool WIDE>
+// SZ: bytes per element (4, or 8 for the FP64 form, which addresses with
+// 64-bit pointers: the buffer form above moves dwords only)
+template <int KIND, bool WIDE, int SZ = 4>
 struct Lanes {
+  static_assert(SZ == 4 || (SZ == 8 && WIDE), "FP64 arrays use the 64-bit address form");
   LaneRef<WIDE> par, cov, hp, hc, ck;
   int64_t es, n;
   // L: layers of the hit arrays; Lck: slots of the checkpoint array
@@ -160,21 +165,21 @@ struct Lanes {
       const int64_t B = int64_t(1) << lay.shift;
       const int64_t blk = i >> lay.shift, lane = i & (B - 1);
       es = B;
-      par.boff = Off((blk * 6 * B + lane) * 4);
-      cov.boff = Off((blk * 21 * B + lane) * 4);
-      hp.boff = Off((blk * 3 * L * B + lane) * 4);
-      hc.boff = Off((blk * 6 * L * B + lane) * 4);
-      ck.boff = Off((blk * 27 * Lck * B + lane) * 4);
+      par.boff = Off((blk * 6 * B + lane) * SZ);
+      cov.boff = Off((blk * 21 * B + lane) * SZ);
+      hp.boff = Off((blk * 3 * L * B + lane) * SZ);
+      hc.boff = Off((blk * 6 * L * B + lane) * SZ);
+      ck.boff = Off((blk * 27 * Lck * B + lane) * SZ);
     } else if (KIND == KF_AOS) {
       es = 1;
-      par.boff = Off(i * 6 * 4);
-      cov.boff = Off(i * 21 * 4);
-      hp.boff = Off(i * 3 * 4);
-      hc.boff = Off(i * 6 * 4);
-      ck.boff = Off(i * 27 * 4);
+      par.boff = Off(i * 6 * SZ);
+      cov.boff = Off(i * 21 * SZ);
+      hp.boff = Off(i * 3 * SZ);
+      hc.boff = Off(i * 6 * SZ);
+      ck.boff = Off(i * 27 * SZ);
     } else {
       es = n;
-      par.boff = cov.boff = hp.boff = hc.boff = ck.boff = Off(i * 4);
+      par.boff = cov.boff = hp.boff = hc.boff = ck.boff = Off(i * SZ);
     }
     if (!WIDE) {
       par.bytes = uint32_t(layout_floats(n, 6, 1, lay) * 4);
@@ -185,8 +190,9 @@ struct Lanes {
     }
   }
   // E consecutive elements of one layer (AoS records) from / to array `base`
-  template <int E>
-  __device__ __forceinline__ void ld_all(const LaneRef<WIDE>& r, const float* base, int l, float* dst) const {
+  template <int E, class T>
+  __device__ __forceinline__ void ld_all(const LaneRef<WIDE>& r, const T* base, int l, T* dst) const {
+    static_assert(sizeof(T) == SZ, "element size");
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {
@@ -202,8 +208,9 @@ struct Lanes {
       for (int e = 0; e < E; ++e) dst[e] = *r.at(base, uni(E, l, e));
     }
   }
-  template <int E>
-  __device__ __forceinline__ void st_all(const LaneRef<WIDE>& r, float* base, int l, const float* src) const {
+  template <int E, class T>
+  __device__ __forceinline__ void st_all(const LaneRef<WIDE>& r, T* base, int l, const T* src) const {
+    static_assert(sizeof(T) == SZ, "element size");
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {

@@ -7,11 +7,13 @@
 
 namespace kf {
 
-template <int KIND, bool WIDE>
+// T: the arrays' scalar (float; double in the FP64 form, which addresses with
+// 64-bit pointers, WIDE).
+template <int KIND, bool WIDE, class T = float>
 struct LaidOutState {
-  const StepArgs& a;
-  const Lanes<KIND, WIDE>& ln;
-  __device__ __forceinline__ bool load(float p[6], float C[21]) const {
+  const StepArgsT<T>& a;
+  const Lanes<KIND, WIDE, sizeof(T)>& ln;
+  __device__ __forceinline__ bool load(T p[6], T C[21]) const {
     ln.template ld_all<6>(ln.par, a.par_in, 0, p);
     ln.template ld_all<21>(ln.cov, a.cov_in, 0, C);
     bool ok = true;
@@ -21,30 +23,31 @@ struct LaidOutState {
     for (int e = 0; e < 21; ++e) ok = ok & fin(C[e]);
     return ok;
   }
-  __device__ __forceinline__ void store(const float p[6], const float C[21]) const {
+  __device__ __forceinline__ void store(const T p[6], const T C[21]) const {
     ln.template st_all<6>(ln.par, a.par_out, 0, p);
     ln.template st_all<21>(ln.cov, a.cov_out, 0, C);
   }
 };
 
-template <int KIND, bool WIDE>
+template <int KIND, bool WIDE, class T = float>
 struct LaidOutHits {
   using Off = typename LaneRef<WIDE>::Off;
-  const StepArgs& a;
-  const Lanes<KIND, WIDE>& ln;
+  const StepArgsT<T>& a;
+  const Lanes<KIND, WIDE, sizeof(T)>& ln;
   Off hp_last, hc_last;  // this lane's offsets of its last layer
-  __device__ __forceinline__ LaidOutHits(const StepArgs& a_, const Lanes<KIND, WIDE>& ln_, int nl)
+  __device__ __forceinline__ LaidOutHits(const StepArgsT<T>& a_, const Lanes<KIND, WIDE, sizeof(T)>& ln_, int nl)
       : a(a_), ln(ln_) {
     const int last = nl > 0 ? nl - 1 : 0;
     hp_last = ln.template layer_off<3>(ln.hp, last);
     hc_last = ln.template layer_off<6>(ln.hc, last);
   }
-  __device__ __forceinline__ void load(int k, float m[3], float V[6]) const {
+  __device__ __forceinline__ void load(int k, T m[3], T V[6]) const {
     ln.template ld_all<3>(ln.hp, a.hit_pos, k, m);
     ln.template ld_all<6>(ln.hc, a.hit_cov, k, V);
   }
-  // AoS records are fetched into registers; element-major layouts through LDS
-  static constexpr bool kStaged = KIND != KF_AOS;
+  // AoS records (and FP64 arrays) are fetched into registers; element-major
+  // float layouts through LDS
+  static constexpr bool kStaged = KIND != KF_AOS && sizeof(T) == 4;
   __device__ __forceinline__ int next(int k) const { return k + 1 < a.L ? k + 1 : k; }
   // layer min(j, the track's last layer); j is wave-uniform
   __device__ __forceinline__ void stage(int j, float* slot) const {
@@ -54,13 +57,13 @@ struct LaidOutHits {
   }
 };
 
-template <int KIND, bool WIDE>
+template <int KIND, bool WIDE, class T = float>
 struct LaidOutCkpt {
-  const StepArgs& a;
-  const Lanes<KIND, WIDE>& ln;
-  __device__ __forceinline__ void operator()(int k, const float p[6], const float C[21]) const {
+  const StepArgsT<T>& a;
+  const Lanes<KIND, WIDE, sizeof(T)>& ln;
+  __device__ __forceinline__ void operator()(int k, const T p[6], const T C[21]) const {
     if (!a.ckpt || (k & ((1 << a.ck_shift) - 1))) return;
-    float s[27];
+    T s[27];
 #pragma unroll
     for (int e = 0; e < 6; ++e) s[e] = p[e];
 #pragma unroll
@@ -132,6 +135,44 @@ hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a
   const bool wide = needs_wide(a.n, a.L, a.lay);
   if (geom == 0) return wide ? launch_prec<0, true>(prec, block, a, s) : launch_prec<0, false>(prec, block, a, s);
   return wide ? launch_prec<1, true>(prec, block, a, s) : launch_prec<1, false>(prec, block, a, s);
+}
+
+// ---------------------------------------------------------------- FP64 form
+// The same step in FP64 end to end (arrays, field constant, layer table and
+// arithmetic); hits fetched one layer ahead into registers.
+template <int GEOM, int PREC, int KIND>
+__global__ void __launch_bounds__(256) kf_step_kernel_f64(const StepArgsT<double> a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Lanes<KIND, true, 8> ln(i, a.n, a.L, a.lay, a.Lck);
+  int nl = a.nlay ? a.nlay[i] : a.L;
+  nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
+  double chi2;
+  uint32_t status;
+  const LaidOutHits<KIND, true, double> hits(a, ln, nl);
+  RegStager<LaidOutHits<KIND, true, double>, double> stager(hits);
+  run_track<GEOM, PREC>(LaidOutState<KIND, true, double>{a, ln}, hits, stager, NoCkpt{}, nl, a.layer, a.b, chi2,
+                        status);
+  if (a.chi2) a.chi2[i] = chi2;
+  if (a.status) a.status[i] = int32_t(status);
+}
+
+template <int GEOM, int PREC>
+static hipError_t launch_f64_kind(int block, const StepArgsT<double>& a, hipStream_t s) {
+  const int64_t grid = (a.n + block - 1) / block;
+  if (a.lay.kind == KF_AOS)
+    hipLaunchKernelGGL((kf_step_kernel_f64<GEOM, PREC, KF_AOS>), dim3(unsigned(grid)), dim3(block), 0, s, a);
+  else if (a.lay.kind == KF_AOSOA)
+    hipLaunchKernelGGL((kf_step_kernel_f64<GEOM, PREC, KF_AOSOA>), dim3(unsigned(grid)), dim3(block), 0, s, a);
+  else
+    hipLaunchKernelGGL((kf_step_kernel_f64<GEOM, PREC, KF_SOA>), dim3(unsigned(grid)), dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_f64(int geom, int prec, int block, const StepArgsT<double>& a, hipStream_t s) {
+  // prec 0: plain update; 2: Joseph update (both in FP64, as everything here)
+  if (geom == 0) return prec == 2 ? launch_f64_kind<0, PREC_F64_JOSEPH>(block, a, s) : launch_f64_kind<0, PREC_F32>(block, a, s);
+  return prec == 2 ? launch_f64_kind<1, PREC_F64_JOSEPH>(block, a, s) : launch_f64_kind<1, PREC_F32>(block, a, s);
 }
 
 // ---------------------------------------------------------------- pack/unpack

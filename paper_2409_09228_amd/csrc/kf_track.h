@@ -17,14 +17,14 @@ namespace kf {
 // angles d, and chi2 advance in place and 0 is returned; otherwise the status
 // bits, with (p, C, d) left undefined.  ZIN: C carries the zero z row and
 // column of a preceding plane update.
-template <int GEOM, int PREC, bool ZIN>
-__device__ __forceinline__ uint32_t layer_step(float p[6], float C[21], Dir& d, const float m[3], const float V[6],
-                                               float target, float b, float& chi2) {
-  float q[6], Pt[21];
-  const uint32_t fp = propagate<GEOM, ZIN>(p, C, d, target, b, q, Pt);
-  const float phi = q[4], theta = q[5];
-  float dchi;
-  const uint32_t fu = update<GEOM, PREC>(q, Pt, m, V, dchi);
+template <int GEOM, int PREC, bool ZIN, class T>
+__device__ __forceinline__ uint32_t layer_step(T p[6], T C[21], DirT<T>& d, const T m[3], const T V[6], T target, T b,
+                                               T& chi2) {
+  T q[6], Pt[21];
+  const uint32_t fp = propagate<GEOM, ZIN, T>(p, C, d, target, b, q, Pt);
+  const T phi = q[4], theta = q[5];
+  T dchi;
+  const uint32_t fu = update<GEOM, PREC, T>(q, Pt, m, V, dchi);
   rotate_by(d.sp, d.cp, q[4] - phi, q[4]);
   rotate_by(d.st, d.ct, q[5] - theta, q[5]);
 #pragma unroll
@@ -75,20 +75,21 @@ __device__ __forceinline__ void read_slot(const float* slot, int lane, float m[3
 //       layer count and a failing track does not leave the loop early
 //   ckpt(k, p, C): called before layer k (may do nothing)
 struct NoCkpt {
-  __device__ __forceinline__ void operator()(int, const float*, const float*) const {}
+  template <class T>
+  __device__ __forceinline__ void operator()(int, const T*, const T*) const {}
 };
 
 // Hits fetched one layer ahead into registers (AoS records: multi-dword loads
 // serve them better than one-dword copies).  hits.next(k): the in-bounds
 // layer to prefetch after layer k.
-template <class Hits>
+template <class Hits, class T = float>
 struct RegStager {
   static constexpr bool kCooperative = false;
   const Hits& h;
-  float mn[3], Vn[6];
+  T mn[3], Vn[6];
   __device__ __forceinline__ explicit RegStager(const Hits& h_) : h(h_) {}
   __device__ __forceinline__ void begin() { h.load(0, mn, Vn); }
-  __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
+  __device__ __forceinline__ void get(int k, T m[3], T V[6]) {
 #pragma unroll
     for (int e = 0; e < 3; ++e) m[e] = mn[e];
 #pragma unroll
@@ -125,28 +126,29 @@ struct LayerRing {
 
 // Layer k of a track: from the second layer on, a plane step knows the zero
 // z row and column its predecessor left in C.
-template <int GEOM, int PREC>
-__device__ __forceinline__ uint32_t layer_at(int k, float p[6], float C[21], Dir& d, const float m[3],
-                                             const float V[6], float target, float b, float& chi2) {
-  if (GEOM == 0 && k > 0) return layer_step<GEOM, PREC, true>(p, C, d, m, V, target, b, chi2);
-  return layer_step<GEOM, PREC, false>(p, C, d, m, V, target, b, chi2);
+template <int GEOM, int PREC, class T>
+__device__ __forceinline__ uint32_t layer_at(int k, T p[6], T C[21], DirT<T>& d, const T m[3], const T V[6], T target,
+                                             T b, T& chi2) {
+  if (GEOM == 0 && k > 0) return layer_step<GEOM, PREC, true, T>(p, C, d, m, V, target, b, chi2);
+  return layer_step<GEOM, PREC, false, T>(p, C, d, m, V, target, b, chi2);
 }
 
 // The layer loop of one track.  Every lane of the wave that runs a track
 // calls this together (lanes without one are inactive); the stager's
 // wave-level waits rely on that.
-template <int GEOM, int PREC, class State, class Hits, class Stager, class Ckpt>
+// T: the scalar of the state, the hits and the layer table (float, or double
+// in the FP64 form).
+template <int GEOM, int PREC, class State, class Hits, class Stager, class Ckpt, class T>
 __device__ __forceinline__ void run_track(const State& state, const Hits& hits, Stager& stager, const Ckpt& ckpt,
-                                          int nl, const float* layer, float b, float& chi2_out,
-                                          uint32_t& status_out) {
-  float p[6], C[21];
+                                          int nl, const T* layer, T b, T& chi2_out, uint32_t& status_out) {
+  T p[6], C[21];
   uint32_t flags = state.load(p, C) ? 0u : S_NONFINITE;
-  float chi2 = 0.0f;
+  T chi2 = T(0);
   int k = 0;
   if ((Stager::kCooperative || !flags) && nl > 0) {
-    Dir d;
+    DirT<T> d;
     dir_init(p, d);
-    float m[3], V[6];
+    T m[3], V[6];
     stager.begin();
     // the first layer is peeled so that the loop body is the plane step that
     // knows C's zero z row
@@ -186,11 +188,11 @@ __device__ __forceinline__ void run_track(const State& state, const Hits& hits, 
   if (flags) {
     // recompute the state from before the failing layer
     state.load(p, C);
-    chi2 = 0.0f;
-    Dir d;
+    chi2 = T(0);
+    DirT<T> d;
     dir_init(p, d);
     for (int j = 0; j < done; ++j) {
-      float m[3], V[6];
+      T m[3], V[6];
       hits.load(j, m, V);
       layer_at<GEOM, PREC>(j, p, C, d, m, V, layer[j], b, chi2);
     }

@@ -97,6 +97,12 @@ def lib():
                                          ctypes.POINTER(Tune), vp]
         L.kf_chi2_backward_z.restype = ctypes.c_int
         L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
+        d64 = ctypes.c_double
+        for name in ("kf_propagate_update_z_f64", "kf_propagate_update_r_f64"):
+            fn = getattr(L, name)
+            fn.argtypes = [vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, d64, Layout, ctypes.c_uint32, vp, vp,
+                           ctypes.POINTER(Tune), vp]
+            fn.restype = ctypes.c_int
         L.kf_propagate_update_host.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, i32, vp, i64, f32, Layout,
                                                ctypes.c_uint32, vp, vp, i64, i32, ctypes.POINTER(Tune)]
         L.kf_propagate_update_host.restype = ctypes.c_int
@@ -328,6 +334,104 @@ def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
         out["hit_pos"] = pack(soa["hit_pos"], 3, L, n, layout)
         out["hit_cov"] = pack(soa["hit_cov"], 6, L, n, layout)
     return out
+
+
+def to_layout_np(arr, layout) -> np.ndarray:
+    """Logical [n, E] or [L, n, E] -> the flat array of `layout` (numpy, any
+    dtype): SoA e*n + i (per layer (l*E + e)*n + i); AoS i*E + e; AoSoA-B
+    ((i/B)*L + l)*E*B + e*B + i%B (L = 1 for per-track arrays)."""
+    a = np.asarray(arr)
+    per_layer = a.ndim == 3
+    if not per_layer:
+        a = a[None]
+    L, n, E = a.shape
+    kind, B = layout
+    if kind == KF_SOA:
+        out = a.transpose(0, 2, 1)
+    elif kind == KF_AOS:
+        out = a
+    else:
+        nb = (n + B - 1) // B
+        pad = np.zeros((L, nb * B, E), a.dtype)
+        pad[:, :n] = a
+        out = pad.reshape(L, nb, B, E).transpose(1, 0, 3, 2)
+    return np.ascontiguousarray(out).reshape(-1)
+
+
+def from_layout_np(flat, n_elem: int, n_layers: int, n: int, layout) -> np.ndarray:
+    """Inverse of to_layout_np: logical [n, E] (n_layers = 1) or [L, n, E]."""
+    kind, B = layout
+    f = np.asarray(flat)
+    if kind == KF_SOA:
+        a = f.reshape(n_layers, n_elem, n).transpose(0, 2, 1)
+    elif kind == KF_AOS:
+        a = f.reshape(n_layers, n, n_elem)
+    else:
+        nb = (n + B - 1) // B
+        a = f.reshape(nb, n_layers, n_elem, B).transpose(1, 0, 3, 2).reshape(n_layers, nb * B, n_elem)[:, :n]
+    return a[0] if n_layers == 1 else a
+
+
+def stage_sample_f64(sample: dict, layout=SOA, device="cuda") -> dict:
+    """The sample as FP64 device tensors in `layout` (for the FP64 form)."""
+    import torch
+    n = sample["par"].shape[0]
+    L = sample["hit_pos"].shape[0]
+    geom = int(sample["geom"][0]) if n else 0
+    up = lambda x: torch.from_numpy(to_layout_np(np.asarray(x, np.float64), layout)).to(device)
+    return {"n": n, "L": L, "layout": layout, "bz": float(sample["bz"]), "geom": geom, "dtype": "f64",
+            "par": up(sample["par"]), "cov": up(sample["cov"]), "hit_pos": up(sample["hit_pos"]),
+            "hit_cov": up(sample["hit_cov"]),
+            "nlay": torch.from_numpy(np.ascontiguousarray(sample["nlay"], np.int32)).to(device),
+            "layers": np.asarray(sample["layer_z"] if geom == 0 else sample["layer_r"], np.float64)[:L]}
+
+
+class StepLauncherF64:
+    """A kf_propagate_update_z_f64/_r_f64 call on a stage_sample_f64 sample
+    with every argument converted once; outputs (FP64 arrays in the sample's
+    layout, chi2 float64, status int32) are allocated here unless given."""
+
+    def __init__(self, st: dict, flags: int = 0, tune=None, stream=None, out=None, nlay=True):
+        import torch
+        _require_cuda(st["par"], st["cov"], st["hit_pos"], st["hit_cov"])
+        n = st["n"]
+        dev = st["par"].device
+        self.par_out, self.cov_out = out if out is not None else (torch.empty_like(st["par"]),
+                                                                  torch.empty_like(st["cov"]))
+        self.chi2 = torch.empty(n, dtype=torch.float64, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        self._st = st
+        self._layers = np.ascontiguousarray(st["layers"], np.float64)
+        self._tune = None if tune is None else make_tune(tune)
+        self._fn = lib().kf_propagate_update_z_f64 if st["geom"] == 0 else lib().kf_propagate_update_r_f64
+        self._name = "kf_propagate_update_" + ("z" if st["geom"] == 0 else "r") + "_f64"
+        with torch.cuda.device(dev):
+            sp = _stream(stream)
+        self._args = (_ptr(st["par"]), _ptr(st["cov"]), _ptr(self.par_out), _ptr(self.cov_out), _ptr(st["hit_pos"]),
+                      _ptr(st["hit_cov"]), self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]),
+                      _ptr(st["nlay"]) if nlay else None, int(n), float(st["bz"]), Layout(*st["layout"]), int(flags),
+                      _ptr(self.chi2), _ptr(self.status), None if self._tune is None else ctypes.byref(self._tune), sp)
+
+    def __call__(self):
+        rc = self._fn(*self._args)
+        if rc != KF_OK:
+            raise KFError(rc, self._name)
+
+    def logical(self):
+        """Results as logical numpy arrays: par [n, 6], cov [n, 21], chi2, status."""
+        import torch
+        torch.cuda.synchronize(self.par_out.device)
+        n, lay = self._st["n"], self._st["layout"]
+        return (from_layout_np(self.par_out.cpu().numpy(), 6, 1, n, lay),
+                from_layout_np(self.cov_out.cpu().numpy(), 21, 1, n, lay),
+                self.chi2.cpu().numpy(), self.status.cpu().numpy())
+
+
+def run_f64(st: dict, flags: int = 0, tune=None, stream=None, nlay=True):
+    """One FP64 step on a stage_sample_f64 sample; logical numpy results."""
+    launch = StepLauncherF64(st, flags=flags, tune=tune, stream=stream, nlay=nlay)
+    launch()
+    return launch.logical()
 
 
 def stage_host(sample: dict, layout=SOA, pinned: bool = True) -> dict:

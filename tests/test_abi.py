@@ -26,7 +26,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_strings():
-    assert K.lib().kf_abi_version() == 4
+    assert K.lib().kf_abi_version() == 5
     assert K.status_string(0) == "ok"
     assert "layout" in K.status_string(3)
 
@@ -103,4 +103,25 @@ def test_host_pipeline_validation_before_any_device_call():
     assert call(flags=256) == 8
     assert call(par=None) == 1
     assert call(par=ctypes.c_void_p(4098)) == 4
+    assert call(n=0) == 0
+
+
+@pytest.mark.parametrize("fn", ["kf_propagate_update_z_f64", "kf_propagate_update_r_f64"])
+def test_f64_validation_before_any_device_call(fn):
+    lib = K.lib()
+    layers = (ctypes.c_double * 4)(10, 15, 20, 25)
+    h = ctypes.c_void_p(4096)
+
+    def call(n=10, L=3, layout=K.SOA, flags=0, par=h, chi2=None, tune=None):
+        tn = None if tune is None else ctypes.byref(K.Tune(*tune))
+        return getattr(lib, fn)(par, h, h, h, h, h, ctypes.cast(layers, ctypes.c_void_p), L, None, n, 3.8,
+                                K.Layout(*layout), flags, chi2, None, tn, None)
+    assert call(n=-1) == 2
+    assert call(L=65) == 2
+    assert call(layout=(1, 24)) == 3
+    assert call(flags=4) == 8
+    assert call(tune=(100, 1)) == 8
+    assert call(par=None) == 1
+    assert call(par=ctypes.c_void_p(4100)) == 4          # 4-aligned is not enough for doubles
+    assert call(chi2=ctypes.c_void_p(4100)) == 4
     assert call(n=0) == 0

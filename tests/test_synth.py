@@ -52,3 +52,27 @@ def test_uneven_mix():
     hp, hc, off = S.to_ragged(u["hit_pos"][:, :100], u["hit_cov"][:, :100], u["nlay"][:100])
     assert hp.shape[0] == u["nlay"][:100].sum()
     np.testing.assert_array_equal(hp[off[7] + 3], u["hit_pos"][3, 7])
+
+
+def test_host_layout_roundtrip():
+    """The numpy layout builder of the FP64 form agrees with the offset formula
+    of the library's layouts and inverts exactly."""
+    from paper_2409_09228_amd import kf as K
+    rng = np.random.default_rng(5)
+    n, L, E = 100, 3, 7
+    x = rng.normal(size=(L, n, E))
+    for lay in (K.SOA, K.AOS, K.aosoa(16), K.aosoa(64)):
+        f = K.to_layout_np(x, lay)
+        np.testing.assert_array_equal(K.from_layout_np(f, E, L, n, lay), x)
+        i, l, e = 77, 2, 5
+        kind, B = lay
+        if kind == K.KF_SOA:
+            o = (l * E + e) * n + i
+        elif kind == K.KF_AOS:
+            o = (l * n + i) * E + e
+        else:
+            o = (i // B) * (E * L * B) + (i % B) + (l * E + e) * B
+        assert f[o] == x[l, i, e]
+    y = rng.normal(size=(n, E))
+    for lay in (K.SOA, K.AOS, K.aosoa(32)):
+        np.testing.assert_array_equal(K.from_layout_np(K.to_layout_np(y, lay), E, 1, n, lay), y)
