@@ -51,6 +51,9 @@ def lib():
         L.kfo_update.argtypes = [d, d, d, d, c_int, d, d, d, u32]
         L.kfo_grad_chi2.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, c_int]
         L.kfo_grad_chi2_f32.argtypes = L.kfo_grad_chi2.argtypes
+        L.kfo_filter_record.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, d, d, d,
+                                        i32, c_int, c_int]
+        L.kfo_filter_record.restype = ctypes.c_int
         for fn in (L.kfo_run_f64, L.kfo_run_f32, L.kfo_propagate, L.kfo_update, L.kfo_grad_chi2,
                    L.kfo_grad_chi2_f32):
             fn.restype = ctypes.c_int
@@ -158,6 +161,122 @@ def grad_chi2(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, w=None, 
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return gh, gp
+
+
+def filter_record(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, nlay=None, joseph=False,
+                  precision: str = "f64", nthreads=None) -> dict:
+    """The filter pass with what it computes on every layer k it applies:
+    pred_p [L, n, 6] / pred_P [L, n, 6, 6] (propagated to layer k, before the
+    update), F [L, n, 6, 6] (Jacobian of that propagation), filt_p / filt_P
+    (after the update); plus chi2 [n] and status [n] as ``run`` returns them.
+    Entries of layers a track did not apply are zero.  precision="f32" runs
+    the filter in float arithmetic (tolerance sizing)."""
+    par = np.ascontiguousarray(par, np.float64)
+    cov = np.ascontiguousarray(cov, np.float64)
+    hit_pos = np.ascontiguousarray(hit_pos, np.float64)
+    hit_cov = np.ascontiguousarray(hit_cov, np.float64)
+    layers = np.ascontiguousarray(layers, np.float64)
+    n = par.shape[0]
+    L = hit_pos.shape[0]
+    nl = None if nlay is None else np.ascontiguousarray(nlay, np.int32)
+    out = {k: np.zeros((L, n, w)) for k, w in (("pred_p", 6), ("pred_P", 21), ("F", 36), ("filt_p", 6),
+                                               ("filt_P", 21))}
+    chi2 = np.zeros(n)
+    status = np.zeros(n, np.int32)
+    c = ctypes.c_double
+    rc = lib().kfo_filter_record(int(geom), n, L, _p(layers, c), float(bz), _p(nl, ctypes.c_int32), _p(par, c),
+                                 _p(cov, c), _p(hit_pos, c), _p(hit_cov, c), int(bool(joseph)),
+                                 _p(out["pred_p"], c), _p(out["pred_P"], c), _p(out["F"], c),
+                                 _p(out["filt_p"], c), _p(out["filt_P"], c), _p(chi2, c),
+                                 _p(status, ctypes.c_int32), 0 if precision == "f64" else 1, _threads(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    out["pred_P"] = unpack_sym(out["pred_P"])
+    out["filt_P"] = unpack_sym(out["filt_P"])
+    out["F"] = out["F"].reshape(L, n, 6, 6)
+    out["chi2"] = chi2
+    out["status"] = status
+    return out
+
+
+def surface_basis(geom: int, p) -> np.ndarray:
+    """[..., 6, 5]: orthonormal basis of the directions in which a state on
+    its surface can vary -- the surface's five local coordinates.  On a plane
+    z is fixed (x, y, kappa, phi, theta remain); on a cylinder the position
+    moves along the tangent (-y, x)/r and along z."""
+    p = np.asarray(p, np.float64)
+    U = np.zeros(p.shape[:-1] + (6, 5))
+    if geom == 0:
+        for j, a in enumerate((0, 1, 3, 4, 5)):
+            U[..., a, j] = 1.0
+    else:
+        r = np.hypot(p[..., 0], p[..., 1])
+        r = np.where(r > 0, r, 1.0)
+        U[..., 0, 0] = -p[..., 1] / r
+        U[..., 1, 0] = p[..., 0] / r
+        for j, a in enumerate((2, 3, 4, 5)):
+            U[..., a, j + 1] = 1.0
+    return U
+
+
+def smooth(geom: int, par, cov, hit_pos, hit_cov, layers, bz: float, nlay=None, joseph=False,
+           precision: str = "f64", nthreads=None, rec=None):
+    """Rauch-Tung-Striebel smoother after the filter (the backward pass that
+    turns the filter of Sec. 3.1 into a complete track fit): with the filtered
+    state (p_k, C_k) on layer k, the prediction (q, P) and Jacobian F of the
+    propagation from layer k to k + 1, and the smoothed state on k + 1,
+
+        A    = C_k F^T P^-1
+        p_k' = p_k + A (p_{k+1}' - q)
+        C_k' = C_k + A (C_{k+1}' - P) A^T,
+
+    starting from the filtered state of the last layer applied.  A state on a
+    surface has five free coordinates (its covariance is singular along the
+    surface normal in the six global ones), so every matrix above is taken in
+    the local coordinates of its surface (``surface_basis`` at the predicted
+    point: C_loc = U^T C U, F_loc = U_{k+1}^T F U_k, a displacement d maps to
+    U^T d, and back by U).  Process noise is zero, as in the filter.
+
+    Returns (sm_p [L, n, 6], sm_P [L, n, 21] packed, status [n], rec); layers
+    a track did not apply are zero.  precision="f32": the filter and the
+    recursion in float arithmetic (tolerance sizing)."""
+    if rec is None:
+        rec = filter_record(geom, par, cov, hit_pos, hit_cov, layers, bz, nlay, joseph, precision, nthreads)
+    dt = np.float64 if precision == "f64" else np.float32
+    L, n = rec["filt_p"].shape[:2]
+    done = (rec["status"] >> 16).astype(np.int64)
+    sm_p = np.zeros((L, n, 6))
+    sm_P = np.zeros((L, n, 6, 6))
+    last = done - 1
+    have = done > 0
+    idx = np.nonzero(have)[0]
+    sm_p[last[idx], idx] = rec["filt_p"][last[idx], idx]
+    sm_P[last[idx], idx] = rec["filt_P"][last[idx], idx]
+    for k in range(L - 2, -1, -1):
+        t = np.nonzero(k < done - 1)[0]
+        if t.size == 0:
+            continue
+        Uk = surface_basis(geom, rec["pred_p"][k, t]).astype(dt)
+        Un = surface_basis(geom, rec["pred_p"][k + 1, t]).astype(dt)
+        UkT = np.swapaxes(Uk, -1, -2)
+        UnT = np.swapaxes(Un, -1, -2)
+        Ck = UkT @ rec["filt_P"][k, t].astype(dt) @ Uk
+        Fl = UnT @ rec["F"][k + 1, t].astype(dt) @ Uk
+        Pn = UnT @ rec["pred_P"][k + 1, t].astype(dt) @ Un
+        A = Ck @ np.swapaxes(Fl, -1, -2) @ np.linalg.inv(Pn)
+        d = UnT @ (sm_p[k + 1, t] - rec["pred_p"][k + 1, t]).astype(dt)[..., None]
+        sm_p[k, t] = rec["filt_p"][k, t] + (Uk @ (A @ d))[..., 0]
+        Cs = Ck + A @ (UnT @ sm_P[k + 1, t].astype(dt) @ Un - Pn) @ np.swapaxes(A, -1, -2)
+        sm_P[k, t] = Uk @ Cs @ UkT
+    return sm_p, pack_sym(sm_P), rec["status"], rec
+
+
+def smooth_sample(sample: dict, **kw):
+    """``smooth`` on a synthetic sample (single geometry)."""
+    g = int(sample["geom"][0])
+    layers = sample["layer_z"] if g == 0 else sample["layer_r"]
+    return smooth(g, sample["par"], sample["cov"], sample["hit_pos"], sample["hit_cov"], layers, sample["bz"],
+                  nlay=sample["nlay"], **kw)
 
 
 def unpack_sym(P21) -> np.ndarray:

@@ -333,11 +333,25 @@ template <class S, size_t N> bool finite_vec(const std::array<S, N>& a) {
   return true;
 }
 
+// What the filter passes through on layer k, kept for the smoother: the
+// predicted state (before the update), the Jacobian of the propagation into
+// layer k, and the filtered state (after the update).
+template <class S>
+struct LayerRecord {
+  V6<S> pred_p;
+  M6<S> pred_P;
+  M6<S> F;
+  V6<S> filt_p;
+  M6<S> filt_P;
+};
+
 // One track through its layers (Sec. 3.1: propagate the seed to the next
-// layer, update with the one hit on that layer, repeat).
+// layer, update with the one hit on that layer, repeat).  rec: NULL, or room
+// for nl records (filled for the layers applied).
 template <class S>
 void run_track(int geom, V6<S>& p, M6<S>& P, const V3<S>* hits, const M3<S>* hcov,
-               const double* layers, int nl, double b, bool joseph, S& chi2, uint32_t& status) {
+               const double* layers, int nl, double b, bool joseph, S& chi2, uint32_t& status,
+               LayerRecord<S>* rec = nullptr) {
   uint32_t flags = 0;
   int done = 0;
   chi2 = S(0.0);
@@ -355,9 +369,18 @@ void run_track(int geom, V6<S>& p, M6<S>& P, const V3<S>* hits, const M3<S>* hco
       break;
     }
     M6<S> Pt = matmul<S, 6, 6, 6>(matmul<S, 6, 6, 6>(F, P), transpose<S, 6, 6>(F));
+    if (rec) {
+      rec[k].pred_p = pt;
+      rec[k].pred_P = Pt;
+      rec[k].F = F;
+    }
     S dchi;
     if (!kalman_update(pt, Pt, hits[k], hcov[k], joseph, dchi, f)) { flags |= f; break; }
     if (!finite_vec(pt) || !finite_mat(Pt) || !finite_all(dchi)) { flags |= ST_NONFINITE; break; }
+    if (rec) {
+      rec[k].filt_p = pt;
+      rec[k].filt_P = Pt;
+    }
     p = pt;
     P = Pt;
     chi2 = chi2 + dchi;
@@ -403,6 +426,54 @@ void run_batch(int geom, int64_t n, int L, const double* layers, double bz, cons
       for (int a = 0; a < 6; ++a) par_out[i * 6 + a] = p[a];
       for (int a = 0; a < 6; ++a) for (int c = 0; c <= a; ++c) cov_out[i * 21 + pk(a, c)] = P[a][c];
       if (chi2_out) chi2_out[i] = chi2;
+      if (status_out) status_out[i] = int32_t(st);
+    }
+  }
+}
+
+// The filter pass with its per-layer records written out (input to the
+// smoother): pred_p, filt_p [L][n][6]; pred_P, filt_P [L][n][21] packed;
+// F [L][n][36] row-major.  Records of layers a track did not apply are left
+// as they are.  S: the arithmetic (double; float only to size tolerances).
+template <class S>
+void record_batch(int geom, int64_t n, int L, const double* layers, double bz, const int32_t* nlay,
+                  const double* par_in, const double* cov_in, const double* hit_pos, const double* hit_cov,
+                  int joseph, double* pred_p, double* pred_P, double* F, double* filt_p, double* filt_P,
+                  double* chi2_out, int32_t* status_out, int nthreads) {
+  const double b = kCLight * bz;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    std::vector<V3<S>> m(L > 0 ? L : 1);
+    std::vector<M3<S>> V(L > 0 ? L : 1);
+    std::vector<LayerRecord<S>> rec(L > 0 ? L : 1);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      V6<S> p; M6<S> P;
+      load_track<S, double>(i, n, L, par_in, cov_in, hit_pos, hit_cov, p, P, m.data(), V.data());
+      int nl = nlay ? nlay[i] : L;
+      nl = std::max(0, std::min(nl, L));
+      S chi2; uint32_t st;
+      run_track<S>(geom, p, P, m.data(), V.data(), layers, nl, b, joseph != 0, chi2, st, rec.data());
+      const int done = int(st >> 16);
+      for (int k = 0; k < done; ++k) {
+        const int64_t o = int64_t(k) * n + i;
+        const LayerRecord<S>& r = rec[size_t(k)];
+        for (int a = 0; a < 6; ++a) {
+          pred_p[o * 6 + a] = double(r.pred_p[a]);
+          filt_p[o * 6 + a] = double(r.filt_p[a]);
+          for (int c = 0; c < 6; ++c) F[o * 36 + a * 6 + c] = double(r.F[a][c]);
+          for (int c = 0; c <= a; ++c) {
+            pred_P[o * 21 + pk(a, c)] = double(r.pred_P[a][c]);
+            filt_P[o * 21 + pk(a, c)] = double(r.filt_P[a][c]);
+          }
+        }
+      }
+      if (chi2_out) chi2_out[i] = double(chi2);
       if (status_out) status_out[i] = int32_t(st);
     }
   }
@@ -498,6 +569,22 @@ int kfo_run_f32(int geom, int64_t n, int L, const double* layers, double bz, con
   if (n < 0 || L < 0 || (geom != 0 && geom != 1)) return 1;
   kfo::run_batch<float>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph,
                         par_out, cov_out, chi2_out, status_out, nthreads);
+  return 0;
+}
+
+// The filter pass with per-layer records (see record_batch); precision 0:
+// double, 1: float arithmetic (tolerance sizing only).
+int kfo_filter_record(int geom, int64_t n, int L, const double* layers, double bz, const int32_t* nlay,
+                      const double* par_in, const double* cov_in, const double* hit_pos, const double* hit_cov,
+                      int joseph, double* pred_p, double* pred_P, double* F, double* filt_p, double* filt_P,
+                      double* chi2_out, int32_t* status_out, int precision, int nthreads) {
+  if (n < 0 || L < 0 || (geom != 0 && geom != 1)) return 1;
+  if (precision == 0)
+    kfo::record_batch<double>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, pred_p,
+                              pred_P, F, filt_p, filt_P, chi2_out, status_out, nthreads);
+  else
+    kfo::record_batch<float>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, pred_p,
+                             pred_P, F, filt_p, filt_P, chi2_out, status_out, nthreads);
   return 0;
 }
 
