@@ -349,6 +349,61 @@ def bench_f64(args, sample):
     }
 
 
+def bench_smooth(args, sample):
+    """Filter with per-layer checkpoints, then the RTS smoother writing the
+    smoothed states over the checkpoints (in place); the smoother's launch is
+    what is timed and bounded, the whole fit alongside."""
+    import torch
+    from paper_2409_09228_amd import kf as K
+    layout = parse_layout(args.layout)
+    geom = int(sample["geom"][0])
+    n = sample["par"].shape[0]
+    L = sample["hit_pos"].shape[0]
+    updates = int(sample["nlay"].sum())
+    st = K.stage_sample(sample, layout)
+    stream = torch.cuda.current_stream()
+    ck = K.checkpoint_buffer(n, L, layout, "cuda")
+    po, co = torch.empty_like(st["par"]), torch.empty_like(st["cov"])
+    c2 = torch.empty(n, device="cuda")
+    ss = torch.empty(n, dtype=torch.int32, device="cuda")
+    fwd = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
+                         out=(po, co), chi2=c2, status=ss, nlay=st["nlay"], layout=layout, ckpt=ck, ckpt_every=1,
+                         tune=(args.block, 1), stream=stream)
+    out = K.checkpoint_buffer(n, L, layout, "cuda")
+    sm = K.SmoothLauncher(st, ck, po, co, ss, out=out, tune=(args.block, 1), stream=stream)
+    fwd()
+    for _ in range(args.warmup):
+        sm()
+    ms_smooth = time_launches(sm, args.steps, stream)
+
+    def fit():
+        fwd()
+        sm()
+    ms_fit = time_launches(fit, max(args.steps // 2, 1), stream)
+    ms_fwd = time_launches(fwd, max(args.steps // 2, 1), stream)
+    done = int((ss >> 16).sum().item())
+    # algorithmic bytes of the smoother: per applied layer the filtered
+    # parameters (24 B, layers 0 .. done-2) and the smoothed state (108 B);
+    # per track the final state (108 B) and the status word (4 B)
+    bytes_ = 108 * done + 24 * (done - n) + (108 + 4) * n
+    sec = ms_smooth / 1e3
+    hbm = bytes_ / sec / 1e9
+    roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None,
+            "hbm_algorithmic_bytes_per_launch": int(bytes_), "kernel": "kf_smooth_kernel<%d,%s>" % (geom, args.layout)}
+    return {
+        "metric": METRIC + " -- RTS smoother (smoothed track-layer states/s)",
+        "value": round(done / sec, 1), "unit": "smoothed track-layer states/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_smooth, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "form": "filter with checkpoints + RTS smoother", "tracks": n,
+                   "updates_per_step": updates, "smoothed_states": done, "layout": args.layout,
+                   "filter_with_checkpoints_ms": round(ms_fwd, 4), "fit_and_smooth_ms": round(ms_fit, 4),
+                   "fit_and_smooth_tracks_per_s": round(n / (ms_fit / 1e3), 1)},
+        "roofline": roof,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -365,9 +420,9 @@ def main(argv=None):
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
                     help="batched form: search the launch shape first and time the winner")
-    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64"],
+    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64", "smooth"],
                     help="auto: batched for mixed-geometry workloads, plain otherwise; host: host-resident "
-                         "arrays, transfers included; f64: the full-FP64 form")
+                         "arrays, transfers included; f64: the full-FP64 form; smooth: filter + RTS smoother")
     ap.add_argument("--chunk", type=int, default=0, help="host form: tracks per chunk (0: library default)")
     ap.add_argument("--streams", type=int, default=0, help="host form: HIP streams (0: library default)")
     ap.add_argument("--cpu-tracks", type=int, default=480000)
@@ -407,6 +462,9 @@ def main(argv=None):
         return 0
     if args.form == "f64":
         print(json.dumps(bench_f64(args, sample)), flush=True)
+        return 0
+    if args.form == "smooth":
+        print(json.dumps(bench_smooth(args, sample)), flush=True)
         return 0
     if args.form == "batched" or (args.form == "auto" and mixed):
         print(json.dumps(bench_batched(args, sample)), flush=True)

@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 5
+#define KF_ABI_VERSION 6
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -172,9 +172,8 @@ kf_status_t kf_propagate_update_z(
  * x(s)^2 + y(s)^2 - r^2, after a closed-form test that the helix reaches the
  * cylinder at all (KF_S_NO_CROSSING otherwise).  A crossing whose radius still
  * misses r_l by more than 1e-4 * r_l after the five steps sets
- * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z; ckpt_out is
- * not supported here and must be NULL (KF_E_UNSUPPORTED); ckpt_every is then
- * ignored.
+ * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z (the checkpoints
+ * feed kf_smooth).
  */
 kf_status_t kf_propagate_update_r(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,
@@ -182,6 +181,44 @@ kf_status_t kf_propagate_update_r(
     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
     uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out, int32_t ckpt_every,
     const kf_tune_t* tune, void* stream);
+
+/*
+ * kf_smooth -- Rauch-Tung-Striebel smoother after the filter: the backward
+ * pass that turns the filter (Sec. 3.1: propagate to the next layer, update
+ * with its hit, repeat) into a complete track fit, giving every layer the
+ * estimate that uses all of the track's hits.  With the filtered state
+ * (p_k, C_k) on layer k, the prediction q and Jacobian F of the propagation
+ * to layer k + 1 and the smoothed state on layer k + 1:
+ *   p'_k = p_k + A (p'_{k+1} - q),  C'_k = C_k + A (C'_{k+1} - F C_k F^T) A^T,
+ *   A = C_k F^T (F C_k F^T)^-1,
+ * in the five local coordinates of each surface (plane: x, y, kappa, phi,
+ * theta; cylinder: the tangent (-y, x)/r, z, kappa, phi, theta).  The filter
+ * has no process noise, so A = F^-1 and C'_k = F^-1 C'_{k+1} F^-T: the
+ * library evaluates that form (F^-1 in closed form) and never reads C_k.
+ *
+ *   geometry     0: planes (kf_propagate_update_z), 1: cylinders (_r)
+ *   ckpt         the filter's ckpt_out written with ckpt_every = 1 (slot k =
+ *                the state entering layer k): slots 0 .. applied - 1 are read,
+ *                their first six numbers only (parameters)
+ *   par_out, cov_out   the filter's outputs (state after its last layer)
+ *   status       the filter's status words: track i is smoothed over its
+ *                first (status >> 16) layers; the flags are not looked at
+ *   layers, n_layers, n_tracks, bz_tesla, layout   as in the filter call
+ *   smoothed     [n_layers] slots of 27 numbers per track in `layout`
+ *                (kf_checkpoint_floats(n, L, 1, layout) floats): slot k
+ *                receives the smoothed state on layer k (parameters, then the
+ *                packed covariance) for k < applied; other slots are left
+ *                untouched.  May be `ckpt` itself (each slot is read before
+ *                it is written); must not overlap it otherwise.
+ *   tune         NULL or a launch shape (block_threads 64, 128 or 256)
+ * Errors: KF_E_SHAPE (geometry, sizes), KF_E_LAYOUT, KF_E_NULL, KF_E_ALIGN,
+ * KF_E_FLAGS (tune), KF_E_DEVICE, KF_E_LAUNCH; nothing is enqueued on error.
+ * A degenerate step (F not invertible: a crossing tangent to the cylinder)
+ * gives non-finite smoothed values for that track.
+ */
+kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out, const float* cov_out,
+                      const int32_t* status, const float* layers, int32_t n_layers, int64_t n_tracks,
+                      float bz_tesla, kf_layout_t layout, float* smoothed, const kf_tune_t* tune, void* stream);
 
 /*
  * kf_chi2_backward_z -- adjoint of L = sum_i grad_chi2[i] * chi2_i for the plane

@@ -78,7 +78,6 @@ kf_status_t step(int geom, const float* par_in, const float* cov_in, float* par_
         tune->waves_mult > 8)
       return KF_E_FLAGS;
   }
-  if (geom == 1 && ckpt_out) return KF_E_UNSUPPORTED;
   if (n_tracks == 0) return KF_OK;
   if (!par_in || !cov_in || !par_out || !cov_out) return KF_E_NULL;
   if (n_layers > 0 && (!hit_pos || !hit_cov || !layers)) return KF_E_NULL;
@@ -273,6 +272,40 @@ kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const f
   a.b = float(kCLight * double(bz_tesla));
   for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layer_z[l] : 0.0f;
   const hipError_t e = kf::launch_adjoint_z(block, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
+kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out, const float* cov_out,
+                      const int32_t* status, const float* layers, int32_t n_layers, int64_t n_tracks, float bz_tesla,
+                      kf_layout_t layout, float* smoothed, const kf_tune_t* tune, void* stream) {
+  if (geometry != 0 && geometry != 1) return KF_E_SHAPE;
+  if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  int block = 256;
+  if (tune) {
+    block = tune->block_threads;
+    if (block != 64 && block != 128 && block != 256) return KF_E_FLAGS;
+  }
+  if (n_tracks == 0 || n_layers == 0) return KF_OK;
+  if (!ckpt || !par_out || !cov_out || !status || !layers || !smoothed) return KF_E_NULL;
+  const void* ptrs[] = {ckpt, par_out, cov_out, status, smoothed};
+  for (const void* p : ptrs)
+    if (!aligned4(p)) return KF_E_ALIGN;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  kf::SmoothArgs a;
+  a.ckpt = ckpt;
+  a.par = par_out;
+  a.cov = cov_out;
+  a.status = status;
+  a.smoothed = smoothed;
+  a.n = n_tracks;
+  a.L = n_layers;
+  a.lay = tl;
+  a.b = float(kCLight * double(bz_tesla));
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
+  const hipError_t e = kf::launch_smooth(geometry, block, a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 

@@ -355,11 +355,24 @@ __device__ __forceinline__ void propagate_z(const T p[6], const T C[21], DirT<T>
 // The Jacobian adds to the fixed-s partials the path-length term with
 // grad s = -(x J_s[x,:] + y J_s[y,:]) / (x cos phi' + y sin phi'),
 // which keeps the propagated point on the cylinder to first order.
-// Returns status bits (0 on success): an unreachable cylinder first, then a
-// crossing the iteration did not land on.  d: sin and cos of the direction
-// angles of p on entry, of q on return.
+// Status bits (0 on success): an unreachable cylinder first, then a crossing
+// the iteration did not land on.
+//
+// The non-trivial entries of the cylinder Jacobian F: rows x, y, phi live in
+// columns (x, y, kappa, phi), row z in all six; rows kappa and theta are the
+// identity's.
 template <class T>
-__device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], DirT<T>& d, T rk, T b, T q[6], T Pt[21]) {
+struct CylJac {
+  T x0, x1, x3, x4, y0, y1, y3, y4, z0, z1, z3, z4, z5, f0, f1, f3, f4;
+};
+
+// The crossing q and its Jacobian J; returns the status bits.  d: sin and
+// cos of the direction angles of p on entry, of q on return.  inc (if not
+// NULL): the increments q - p of x, y, z and phi at full precision (entries
+// 0, 1, 2, 4).
+template <class T>
+__device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, T rk, T b, T q[6], CylJac<T>& J,
+                                                      T* inc = nullptr) {
   const T sth = d.st, cth = d.ct, sp = d.sp, cp = d.cp;
   const T om = -b * p[3];
   const T x = p[0], y = p[1];
@@ -406,6 +419,12 @@ __device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], Dir
   q[3] = p[3];
   q[4] = p[4] + om * s;
   q[5] = p[5];
+  if (inc) {
+    inc[0] = dx;
+    inc[1] = dy;
+    inc[2] = s * cot;
+    inc[4] = om * s;
+  }
 
   const T hs2 = 0.5f * s * s;
   const T Jxk = b * hs2 * (sA * sinc + cA * g);   // -b d dx/d omega
@@ -417,12 +436,20 @@ __device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], Dir
   const T dsx = -X * rD, dsy = -Y * rD;
   const T dsk = -(X * Jxk + Y * Jyk) * rD;
   const T dsf = -(X * Jxf + Y * Jyf) * rD;
-  // F rows x, y, phi live in columns (x, y, kappa, phi); row z in all six.
-  const T Fx0 = 1.0f + cP * dsx, Fx1 = cP * dsy, Fx3 = Jxk + cP * dsk, Fx4 = Jxf + cP * dsf;
-  const T Fy0 = sP * dsx, Fy1 = 1.0f + sP * dsy, Fy3 = Jyk + sP * dsk, Fy4 = Jyf + sP * dsf;
-  const T Fz0 = cot * dsx, Fz1 = cot * dsy, Fz3 = cot * dsk, Fz4 = cot * dsf, Fz5 = Jzt;
-  const T Ff0 = om * dsx, Ff1 = om * dsy, Ff3 = Jfk + om * dsk, Ff4 = 1.0f + om * dsf;
+  J.x0 = 1.0f + cP * dsx, J.x1 = cP * dsy, J.x3 = Jxk + cP * dsk, J.x4 = Jxf + cP * dsf;
+  J.y0 = sP * dsx, J.y1 = 1.0f + sP * dsy, J.y3 = Jyk + sP * dsk, J.y4 = Jyf + sP * dsf;
+  J.z0 = cot * dsx, J.z1 = cot * dsy, J.z3 = cot * dsk, J.z4 = cot * dsf, J.z5 = Jzt;
+  J.f0 = om * dsx, J.f1 = om * dsy, J.f3 = Jfk + om * dsk, J.f4 = 1.0f + om * dsf;
+  return !reachable ? S_NO_CROSSING : (!on_surface ? S_NEWTON : 0u);
+}
 
+// Pt = F C F^T for the cylinder Jacobian, on packed covariances.
+template <class T>
+__device__ __forceinline__ void transport_cylinder(const CylJac<T>& J, const T C[21], T Pt[21]) {
+  const T Fx0 = J.x0, Fx1 = J.x1, Fx3 = J.x3, Fx4 = J.x4;
+  const T Fy0 = J.y0, Fy1 = J.y1, Fy3 = J.y3, Fy4 = J.y4;
+  const T Fz0 = J.z0, Fz1 = J.z1, Fz3 = J.z3, Fz4 = J.z4, Fz5 = J.z5;
+  const T Ff0 = J.f0, Ff1 = J.f1, Ff3 = J.f3, Ff4 = J.f4;
   T Wx[6], Wy[6], Wz[6], Wf[6];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
@@ -453,8 +480,18 @@ __device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], Dir
   Pt[ix(5, 3)] = C[ix(5, 3)];
   Pt[ix(5, 4)] = Wf[5];
   Pt[ix(5, 5)] = C[ix(5, 5)];
-  return !reachable ? S_NO_CROSSING : (!on_surface ? S_NEWTON : 0u);
 }
+
+// d: sin and cos of the direction angles of p on entry, of q on return.
+template <class T>
+__device__ __forceinline__ uint32_t propagate_r(const T p[6], const T C[21], DirT<T>& d, T rk, T b, T q[6], T Pt[21]) {
+  CylJac<T> J;
+  const uint32_t st = helix_to_cylinder(p, d, rk, b, q, J);
+  transport_cylinder(J, C, Pt);
+  return st;
+}
+
+
 
 // ----------------------------------------------------------------------------
 // Kalman update with a 3D position hit m, covariance V (packed 6), H = [I3|0]:

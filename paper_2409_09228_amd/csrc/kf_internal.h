@@ -62,6 +62,22 @@ struct AdjointArgs {
 
 hipError_t launch_adjoint_z(int block, const AdjointArgs& a, hipStream_t s);
 
+// Smoother over the layers the filter applied (kf_smooth.hip).
+struct SmoothArgs {
+  const float* ckpt;      // the filter's per-layer checkpoints (stride 1): slot k = state entering layer k
+  const float* par;       // the filter's output: the state after its last layer
+  const float* cov;
+  const int32_t* status;  // the filter's status words (layers applied in bits 16..31)
+  float* smoothed;        // slot k = smoothed state on layer k (may be ckpt itself)
+  int64_t n;
+  int32_t L;
+  TrackLayout lay;
+  float b;
+  float layer[KF_MAX_LAYERS];
+};
+
+hipError_t launch_smooth(int geom, int block, const SmoothArgs& a, hipStream_t s);
+
 // precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
 hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);
 // The FP64 form: FP64 arrays, FP64 arithmetic throughout (prec 0 plain update,

@@ -208,6 +208,25 @@ struct Lanes {
       for (int e = 0; e < E; ++e) dst[e] = *r.at(base, uni(E, l, e));
     }
   }
+  // the first N of the E elements of one layer
+  template <int E, int N, class T>
+  __device__ __forceinline__ void ld_first(const LaneRef<WIDE>& r, const T* base, int l, T* dst) const {
+    static_assert(sizeof(T) == SZ && N <= E, "element size, count");
+    if constexpr (!WIDE) {
+      const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
+      if (KIND == KF_AOS) {
+        buf_ld_rec<N>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
+      } else {
+#pragma unroll
+        for (int e = 0; e < N; ++e) dst[e] = buf_ld(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
+      }
+    } else if (KIND == KF_AOS) {
+      ld_rec<N>(r.at(base, uni(E, l, 0)), dst);
+    } else {
+#pragma unroll
+      for (int e = 0; e < N; ++e) dst[e] = *r.at(base, uni(E, l, e));
+    }
+  }
   template <int E, class T>
   __device__ __forceinline__ void st_all(const LaneRef<WIDE>& r, T* base, int l, const T* src) const {
     static_assert(sizeof(T) == SZ, "element size");

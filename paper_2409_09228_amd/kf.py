@@ -97,6 +97,8 @@ def lib():
                                          ctypes.POINTER(Tune), vp]
         L.kf_chi2_backward_z.restype = ctypes.c_int
         L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
+        L.kf_smooth.argtypes = [i32, vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, ctypes.POINTER(Tune), vp]
+        L.kf_smooth.restype = ctypes.c_int
         d64 = ctypes.c_double
         for name in ("kf_propagate_update_z_f64", "kf_propagate_update_r_f64"):
             fn = getattr(L, name)
@@ -582,6 +584,59 @@ def checkpoint_buffer(n: int, L: int, layout, device="cuda", every: int = 1):
     if every not in (1, 2, 4, 8, 16, 32, 64):
         raise ValueError("the checkpoint stride must be a power of two from 1 to 64")
     return empty_like_layout(27, -(-L // every), n, layout, device)
+
+
+class SmoothLauncher:
+    """A kf_smooth call with every argument converted once: the smoother over
+    the filter results of a staged sample (ckpt written with ckpt_every = 1,
+    the filter's par_out, cov_out and status).  `out`: the smoothed array
+    (a checkpoint_buffer; may be `ckpt` itself), allocated if None."""
+
+    def __init__(self, st: dict, ckpt, par_out, cov_out, status, out=None, tune=None, stream=None):
+        import torch
+        _require_cuda(ckpt, par_out, cov_out, status, out)
+        self.out = checkpoint_buffer(st["n"], st["L"], st["layout"], ckpt.device) if out is None else out
+        self._layers = np.ascontiguousarray(st["layers"], np.float32)
+        self._keep = (ckpt, par_out, cov_out, status)
+        self._tune = None if tune is None else make_tune(tune)
+        with torch.cuda.device(ckpt.device):
+            sp = _stream(stream)
+        self._args = (int(st["geom"]), _ptr(ckpt), _ptr(par_out), _ptr(cov_out), _ptr(status),
+                      self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]), int(st["n"]),
+                      float(st["bz"]), Layout(*st["layout"]), _ptr(self.out),
+                      None if self._tune is None else ctypes.byref(self._tune), sp)
+
+    def __call__(self):
+        rc = lib().kf_smooth(*self._args)
+        if rc != KF_OK:
+            raise KFError(rc, "kf_smooth")
+        return self.out
+
+
+def smooth(st: dict, ckpt, par_out, cov_out, status, out=None, tune=None, stream=None):
+    """kf_smooth once; returns the smoothed array (see SmoothLauncher)."""
+    return SmoothLauncher(st, ckpt, par_out, cov_out, status, out=out, tune=tune, stream=stream)()
+
+
+def fit_smooth(st: dict, flags: int = 0, in_place: bool = False, tune=None, stream=None):
+    """Filter (with per-layer checkpoints) then smoother on a staged sample.
+    Returns (par_out, cov_out, chi2, status, smoothed); with in_place the
+    smoothed states overwrite the checkpoints (no second array)."""
+    ck = checkpoint_buffer(st["n"], st["L"], st["layout"], st["par"].device)
+    po, co, c2, ss = propagate_update(st["geom"], st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                                      st["bz"], st["n"], nlay=st["nlay"], layout=st["layout"], flags=flags,
+                                      ckpt=ck, ckpt_every=1, tune=tune, stream=stream)
+    sm = smooth(st, ck, po, co, ss, out=ck if in_place else None, tune=tune, stream=stream)
+    return po, co, c2, ss, sm
+
+
+def smoothed_to_logical(st: dict, sm):
+    """A smoothed (or checkpoint) array -> logical numpy (par [L, n, 6],
+    cov [L, n, 21]), float64."""
+    a = from_layout_np(sm.detach().cpu().numpy().reshape(-1), 27, st["L"], st["n"], st["layout"]).astype(np.float64)
+    if st["L"] == 1:
+        a = a[None]
+    return a[..., :6], a[..., 6:]
 
 
 def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,

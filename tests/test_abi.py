@@ -26,7 +26,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_strings():
-    assert K.lib().kf_abi_version() == 5
+    assert K.lib().kf_abi_version() == 6
     assert K.status_string(0) == "ok"
     assert "layout" in K.status_string(3)
 
@@ -62,11 +62,8 @@ def test_argument_validation_before_any_device_call(fn):
     assert _call(fn, par=0) == 1         # KF_E_NULL
     assert _call(fn, par=1026) == 4      # KF_E_ALIGN
     assert _call(fn, n=0) == 0           # nothing to do
-    if fn.endswith("_r"):
-        assert _call(fn, ckpt=ctypes.c_void_p(8192)) == 9  # KF_E_UNSUPPORTED
-    else:
-        for bad in (3, 6, 128, -2):
-            assert _call(fn, ckpt=ctypes.c_void_p(8192), every=bad) == 2  # stride not a power of two <= 64
+    for bad in (3, 6, 128, -2):
+        assert _call(fn, ckpt=ctypes.c_void_p(8192), every=bad) == 2  # stride not a power of two <= 64
 
 
 def test_checkpoint_sizes():
@@ -125,3 +122,24 @@ def test_f64_validation_before_any_device_call(fn):
     assert call(par=ctypes.c_void_p(4100)) == 4          # 4-aligned is not enough for doubles
     assert call(chi2=ctypes.c_void_p(4100)) == 4
     assert call(n=0) == 0
+
+
+def test_smooth_validation_before_any_device_call():
+    lib = K.lib()
+    layers = (ctypes.c_float * 4)(10, 15, 20, 25)
+    h = ctypes.c_void_p(4096)
+
+    def call(geom=0, n=10, L=3, layout=K.SOA, ck=h, out=h, tune=None):
+        tn = None if tune is None else ctypes.byref(K.Tune(*tune))
+        return lib.kf_smooth(geom, ck, h, h, h, ctypes.cast(layers, ctypes.c_void_p), L, n, 3.8, K.Layout(*layout),
+                             out, tn, None)
+    assert call(geom=2) == 2
+    assert call(n=-1) == 2
+    assert call(L=65) == 2
+    assert call(layout=(1, 40)) == 3
+    assert call(tune=(32, 1)) == 8
+    assert call(ck=None) == 1
+    assert call(out=None) == 1
+    assert call(out=ctypes.c_void_p(4097)) == 4
+    assert call(n=0) == 0
+    assert call(L=0) == 0
