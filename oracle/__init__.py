@@ -54,6 +54,9 @@ def lib():
         L.kfo_filter_record.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, d, d, d,
                                         i32, c_int, c_int]
         L.kfo_filter_record.restype = ctypes.c_int
+        L.kfo_gate_run.argtypes = [c_int, c_i64, c_int, c_int, d, c_dbl, i32, d, d, d, d, c_dbl, i32, d, d, d,
+                                   i32, i32, d, c_int, c_int]
+        L.kfo_gate_run.restype = ctypes.c_int
         for fn in (L.kfo_run_f64, L.kfo_run_f32, L.kfo_propagate, L.kfo_update, L.kfo_grad_chi2,
                    L.kfo_grad_chi2_f32):
             fn.restype = ctypes.c_int
@@ -277,6 +280,45 @@ def smooth_sample(sample: dict, **kw):
     layers = sample["layer_z"] if g == 0 else sample["layer_r"]
     return smooth(g, sample["par"], sample["cov"], sample["hit_pos"], sample["hit_cov"], layers, sample["bz"],
                   nlay=sample["nlay"], **kw)
+
+
+def gate_run(geom: int, par, cov, cand_pos, cand_cov, layers, bz: float, gate: float, nlay=None, forced=None,
+             precision: str = "f64", nthreads=None) -> dict:
+    """The filter with hit selection among M candidate hits per layer: on
+    every layer the candidate with the smallest update chi-square not above
+    `gate` updates the state, or none (a hole: the state is the prediction).
+    cand_pos [L, n, M, 3], cand_cov [L, n, M, 6]; forced [L, n] int (the
+    choices to follow instead, -1 a hole).  Returns par [n, 6], cov [n, 21],
+    chi2 [n], status [n], chosen [L, n] (-2 where a layer was not processed)
+    and cand_chi2 [L, n, M] (NaN for candidates that take no part)."""
+    par = np.ascontiguousarray(par, np.float64)
+    cov = np.ascontiguousarray(cov, np.float64)
+    cand_pos = np.ascontiguousarray(cand_pos, np.float64)
+    cand_cov = np.ascontiguousarray(cand_cov, np.float64)
+    layers = np.ascontiguousarray(layers, np.float64)
+    L, n, M = cand_pos.shape[:3]
+    nl = None if nlay is None else np.ascontiguousarray(nlay, np.int32)
+    fc = None if forced is None else np.ascontiguousarray(forced, np.int32)
+    out = {"par": np.zeros((n, 6)), "cov": np.zeros((n, 21)), "chi2": np.zeros(n),
+           "status": np.zeros(n, np.int32), "chosen": np.full((L, n), -2, np.int32),
+           "cand_chi2": np.full((L, n, M), np.nan)}
+    c = ctypes.c_double
+    rc = lib().kfo_gate_run(int(geom), n, L, M, _p(layers, c), float(bz), _p(nl, ctypes.c_int32), _p(par, c),
+                            _p(cov, c), _p(cand_pos, c), _p(cand_cov, c), float(gate), _p(fc, ctypes.c_int32),
+                            _p(out["par"], c), _p(out["cov"], c), _p(out["chi2"], c),
+                            _p(out["status"], ctypes.c_int32), _p(out["chosen"], ctypes.c_int32),
+                            _p(out["cand_chi2"], c), 0 if precision == "f64" else 1, _threads(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return out
+
+
+def gate_sample(sample: dict, mh: dict, gate: float, **kw) -> dict:
+    """``gate_run`` on a synthetic sample and its candidate hits (synth.multi_hit)."""
+    g = int(sample["geom"][0])
+    layers = sample["layer_z"] if g == 0 else sample["layer_r"]
+    return gate_run(g, sample["par"], sample["cov"], mh["cand_pos"], mh["cand_cov"], layers, sample["bz"], gate,
+                    nlay=sample["nlay"], **kw)
 
 
 def unpack_sym(P21) -> np.ndarray:

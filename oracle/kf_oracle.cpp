@@ -479,6 +479,122 @@ void record_batch(int geom, int64_t n, int L, const double* layers, double bz, c
   }
 }
 
+// Hit selection on layers with several candidate hits (the search step of
+// track finding that runs between propagation and update, Sec. 3.1): after
+// the propagation, every candidate j gets the chi-square a Kalman update
+// with it would add; a candidate whose residual covariance is not positive
+// definite, or with non-finite values, takes no part.  The candidate with
+// the smallest chi-square not above `gate` (the first of equal ones) updates
+// the state; if none qualifies the layer is passed without update (a hole)
+// and the state is the prediction.  forced (if not NULL): the choice of
+// every layer is taken from it instead (-1: a hole) -- used to follow a
+// given sequence of choices.  Track failures as in run_track.
+// cand_chi2 (if not NULL): [nl][M] each candidate's chi-square, NaN if it
+// takes no part; chosen: [nl] the index used, -1 for a hole.
+template <class S>
+void run_track_gated(int geom, V6<S>& p, M6<S>& P, const V3<S>* cand, const M3<S>* ccov, int M,
+                     const double* layers, int nl, double b, double gate, const int32_t* forced,
+                     S& chi2, uint32_t& status, int32_t* chosen, double* cand_chi2) {
+  uint32_t flags = 0;
+  int done = 0;
+  chi2 = S(0.0);
+  if (!finite_vec(p) || !finite_mat(P)) flags |= ST_NONFINITE;
+  for (int k = 0; k < nl && !flags; ++k) {
+    M6<S> F;
+    uint32_t f = 0;
+    V6<S> pt = propagate(geom, p, layers[k], b, F, f);
+    if (f) { flags |= f; break; }
+    if (!finite_vec(pt) || !finite_mat(F)) { flags |= ST_NONFINITE; break; }
+    M6<S> Pt = matmul<S, 6, 6, 6>(matmul<S, 6, 6, 6>(F, P), transpose<S, 6, 6>(F));
+    int best = -1;
+    double bchi = 0.0;
+    for (int j = 0; j < M; ++j) {
+      V6<S> q = pt;
+      M6<S> Q = Pt;
+      S c;
+      uint32_t fj = 0;
+      const V3<S>& m = cand[size_t(k) * M + j];
+      const M3<S>& V = ccov[size_t(k) * M + j];
+      const bool ok = finite_vec(m) && finite_mat(V) && kalman_update(q, Q, m, V, false, c, fj) &&
+                      finite_all(c);
+      if (cand_chi2) cand_chi2[size_t(k) * M + j] = ok ? val(c) : NAN;
+      if (ok && val(c) <= gate && (best < 0 || val(c) < bchi)) {
+        best = j;
+        bchi = val(c);
+      }
+    }
+    if (forced) best = forced[k];
+    if (chosen) chosen[k] = best;
+    if (best >= 0) {
+      S dchi;
+      if (!kalman_update(pt, Pt, cand[size_t(k) * M + best], ccov[size_t(k) * M + best], false, dchi, f)) {
+        flags |= f;
+        break;
+      }
+      if (!finite_vec(pt) || !finite_mat(Pt) || !finite_all(dchi)) { flags |= ST_NONFINITE; break; }
+      chi2 = chi2 + dchi;
+    }
+    p = pt;
+    P = Pt;
+    done = k + 1;
+  }
+  status = flags | (uint32_t(done) << 16);
+}
+
+// cand_pos [L][n][M][3], cand_cov [L][n][M][6] packed; forced, chosen [L][n];
+// cand_chi2 [L][n][M] (or NULL).
+template <class S>
+void gate_batch(int geom, int64_t n, int L, int M, const double* layers, double bz, const int32_t* nlay,
+                const double* par_in, const double* cov_in, const double* cand_pos, const double* cand_cov,
+                double gate, const int32_t* forced, double* par_out, double* cov_out, double* chi2_out,
+                int32_t* status_out, int32_t* chosen_out, double* cand_chi2_out, int nthreads) {
+  const double b = kCLight * bz;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel
+#endif
+  {
+    const size_t LM = size_t(L > 0 ? L : 1) * size_t(M);
+    std::vector<V3<S>> m(LM);
+    std::vector<M3<S>> V(LM);
+    std::vector<int32_t> fc(size_t(L > 0 ? L : 1)), ch(size_t(L > 0 ? L : 1));
+    std::vector<double> cc(LM);
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+      V6<S> p; M6<S> P;
+      for (int a = 0; a < 6; ++a) p[a] = S(par_in[i * 6 + a]);
+      for (int a = 0; a < 6; ++a) for (int c = 0; c < 6; ++c) P[a][c] = S(cov_in[i * 21 + pk(a, c)]);
+      for (int k = 0; k < L; ++k) {
+        for (int j = 0; j < M; ++j) {
+          const int64_t o = (int64_t(k) * n + i) * M + j;
+          for (int a = 0; a < 3; ++a) m[size_t(k) * M + j][a] = S(cand_pos[o * 3 + a]);
+          for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) V[size_t(k) * M + j][a][c] = S(cand_cov[o * 6 + pk(a, c)]);
+        }
+        if (forced) fc[size_t(k)] = forced[int64_t(k) * n + i];
+      }
+      int nl = nlay ? nlay[i] : L;
+      nl = std::max(0, std::min(nl, L));
+      S chi2; uint32_t st;
+      std::fill(cc.begin(), cc.end(), NAN);
+      run_track_gated<S>(geom, p, P, m.data(), V.data(), M, layers, nl, b, gate, forced ? fc.data() : nullptr,
+                         chi2, st, ch.data(), cc.data());
+      const int done = int(st >> 16);
+      for (int a = 0; a < 6; ++a) par_out[i * 6 + a] = double(p[a]);
+      for (int a = 0; a < 6; ++a) for (int c = 0; c <= a; ++c) cov_out[i * 21 + pk(a, c)] = double(P[a][c]);
+      if (chi2_out) chi2_out[i] = double(chi2);
+      if (status_out) status_out[i] = int32_t(st);
+      for (int k = 0; k < done; ++k) {
+        if (chosen_out) chosen_out[int64_t(k) * n + i] = ch[size_t(k)];
+        if (cand_chi2_out)
+          for (int j = 0; j < M; ++j) cand_chi2_out[(int64_t(k) * n + i) * M + j] = cc[size_t(k) * M + j];
+      }
+    }
+  }
+}
+
 // Reference gradient of sum_i w_i chi2_i with respect to the seed parameters
 // and the hit positions, by forward-mode dual numbers through the whole
 // chain (the Jacobian's own dependence on p enters through nested duals).
@@ -585,6 +701,22 @@ int kfo_filter_record(int geom, int64_t n, int L, const double* layers, double b
   else
     kfo::record_batch<float>(geom, n, L, layers, bz, nlay, par_in, cov_in, hit_pos, hit_cov, joseph, pred_p,
                              pred_P, F, filt_p, filt_P, chi2_out, status_out, nthreads);
+  return 0;
+}
+
+// Filter with hit selection among M candidates per layer (see
+// run_track_gated); precision 0 double, 1 float (tolerance sizing only).
+int kfo_gate_run(int geom, int64_t n, int L, int M, const double* layers, double bz, const int32_t* nlay,
+                 const double* par_in, const double* cov_in, const double* cand_pos, const double* cand_cov,
+                 double gate, const int32_t* forced, double* par_out, double* cov_out, double* chi2_out,
+                 int32_t* status_out, int32_t* chosen_out, double* cand_chi2_out, int precision, int nthreads) {
+  if (n < 0 || L < 0 || M < 1 || (geom != 0 && geom != 1)) return 1;
+  if (precision == 0)
+    kfo::gate_batch<double>(geom, n, L, M, layers, bz, nlay, par_in, cov_in, cand_pos, cand_cov, gate, forced,
+                            par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
+  else
+    kfo::gate_batch<float>(geom, n, L, M, layers, bz, nlay, par_in, cov_in, cand_pos, cand_cov, gate, forced,
+                           par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
   return 0;
 }
 

@@ -283,6 +283,38 @@ def generate(name_or_workload, seed: int | None = None, n_events: int | None = N
     }
 
 
+def multi_hit(sample: dict, n_cand: int, spread: float = 3.0, seed: int = 0) -> dict:
+    """Candidate hits for hit selection: on every layer each track gets its
+    own hit plus n_cand - 1 decoys, at a random position in the list.  A
+    decoy is the track's hit displaced by a Gaussian of sigma
+    spread * SIGMA_HIT per coordinate -- in x, y and z on planes, along
+    r*phi and z on cylinders (decoys stay on the cylinder) -- with the same
+    covariance.  Returns cand_pos [L, n, M, 3], cand_cov [L, n, M, 6] and
+    true_index [L, n]."""
+    hp = np.asarray(sample["hit_pos"], np.float64)
+    L, n = hp.shape[:2]
+    M = int(n_cand)
+    g = np.random.Generator(np.random.Philox(key=[BASE_SEED + 7919 * (seed + 1), M]))
+    true_index = g.integers(0, M, (L, n)).astype(np.int32)
+    off = g.normal(0.0, spread * SIGMA_HIT, (L, n, M, 3))
+    cand = np.repeat(hp[:, :, None, :], M, axis=2)
+    geom = np.asarray(sample["geom"])
+    cyl = geom == GEOM_R
+    if (~cyl).any():
+        cand[:, ~cyl] += off[:, ~cyl]
+    if cyl.any():
+        x, y = cand[:, cyl, :, 0], cand[:, cyl, :, 1]
+        r = np.hypot(x, y)
+        ang = np.arctan2(y, x) + off[:, cyl, :, 0] / np.where(r > 0, r, 1.0)
+        cand[:, cyl, :, 0] = r * np.cos(ang)
+        cand[:, cyl, :, 1] = r * np.sin(ang)
+        cand[:, cyl, :, 2] += off[:, cyl, :, 2]
+    li, ti = np.meshgrid(np.arange(L), np.arange(n), indexing="ij")
+    cand[li, ti, true_index] = hp
+    cov = np.repeat(np.asarray(sample["hit_cov"], np.float64)[:, :, None, :], M, axis=2)
+    return {"cand_pos": cand, "cand_cov": cov, "true_index": true_index, "n_cand": M, "spread": spread}
+
+
 def subset(sample: dict, idx: np.ndarray) -> dict:
     """The same sample restricted to tracks ``idx`` (tracks are independent)."""
     out = dict(sample)
