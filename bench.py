@@ -404,6 +404,54 @@ def bench_smooth(args, sample):
     }
 
 
+def bench_gate(args, sample):
+    """The filter with hit selection: n_cand candidates per layer (the
+    track's hit and decoys at spread x the hit resolution), chi-square gate
+    30; device-resident, timed like the plain form."""
+    import torch
+    from paper_2409_09228_amd import kf as K
+    from paper_2409_09228_amd import synth as S
+    layout = parse_layout(args.layout)
+    geom = int(sample["geom"][0])
+    n = sample["par"].shape[0]
+    M = args.cand
+    mh = S.multi_hit(sample, M, spread=args.spread)
+    st = K.stage_sample(sample, layout)
+    cands = K.stage_candidates(st, mh)
+    del mh
+    stream = torch.cuda.current_stream()
+    run = K.GateLauncher(st, cands, args.gate, tune=(args.block, 1), stream=stream)
+    for _ in range(args.warmup):
+        run()
+    ms = time_launches(run, args.steps, stream)
+    done = int((run.status >> 16).sum().item())
+    ch = run.chosen
+    L = st["L"]
+    proc = torch.arange(L, device="cuda")[:, None] < (run.status >> 16)[None, :]
+    holes = int(((ch == -1) & proc).sum().item())
+    sec = ms / 1e3
+    # algorithmic bytes: per processed layer M candidates (36 B each) and the
+    # choice (4 B); per track the state in and out (216 B), nlay, chi2, status
+    bytes_ = done * (36 * M + 4) + n * (216 + 12)
+    flops = done * (FLOPS_PER_UPDATE[geom] + 44 * M)
+    hbm = bytes_ / sec / 1e9
+    roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm / HBM_PEAK_GBS, 4), "traffic": None, "hbm_algorithmic_bytes_per_launch": int(bytes_),
+            "intensity_flop_per_byte": round(flops / bytes_, 2), "alu_achieved_TFLOPs": round(flops / sec / 1e12, 3),
+            "kernel": "kf_gate_kernel<%d,%s>" % (geom, args.layout)}
+    return {
+        "metric": METRIC + " -- hit selection among candidates (track-layer steps/s)",
+        "value": round(done / sec, 1), "unit": "track-layer steps/s (propagate + select + update)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "form": "hit selection", "tracks": n, "layers_processed": done,
+                   "candidates_per_layer": M, "decoy_spread_sigma": args.spread, "chi2_gate": args.gate,
+                   "hole_fraction": round(holes / max(done, 1), 4), "layout": args.layout,
+                   "candidates_per_s": round(done * M / sec, 1)},
+        "roofline": roof,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,11 +468,14 @@ def main(argv=None):
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
                     help="batched form: search the launch shape first and time the winner")
-    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64", "smooth"],
+    ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64", "smooth", "gate"],
                     help="auto: batched for mixed-geometry workloads, plain otherwise; host: host-resident "
-                         "arrays, transfers included; f64: the full-FP64 form; smooth: filter + RTS smoother")
+                         "arrays, transfers included; f64: the full-FP64 form; smooth: filter + RTS smoother; gate: hit selection")
     ap.add_argument("--chunk", type=int, default=0, help="host form: tracks per chunk (0: library default)")
     ap.add_argument("--streams", type=int, default=0, help="host form: HIP streams (0: library default)")
+    ap.add_argument("--cand", type=int, default=8, help="gate form: candidate hits per layer")
+    ap.add_argument("--spread", type=float, default=10.0, help="gate form: decoy spread in hit sigmas")
+    ap.add_argument("--gate", type=float, default=30.0, help="gate form: chi-square gate")
     ap.add_argument("--cpu-tracks", type=int, default=480000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer --steps times (calibrates the HBM byte counters)")
@@ -465,6 +516,9 @@ def main(argv=None):
         return 0
     if args.form == "smooth":
         print(json.dumps(bench_smooth(args, sample)), flush=True)
+        return 0
+    if args.form == "gate":
+        print(json.dumps(bench_gate(args, sample)), flush=True)
         return 0
     if args.form == "batched" or (args.form == "auto" and mixed):
         print(json.dumps(bench_batched(args, sample)), flush=True)

@@ -64,7 +64,7 @@
 extern "C" {
 #endif
 
-#define KF_ABI_VERSION 6
+#define KF_ABI_VERSION 7
 #define KF_MAX_LAYERS 64
 
 typedef enum {
@@ -181,6 +181,49 @@ kf_status_t kf_propagate_update_r(
     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
     uint32_t flags, float* chi2_out, int32_t* status_out, float* ckpt_out, int32_t ckpt_every,
     const kf_tune_t* tune, void* stream);
+
+/* Most candidate hits per layer kf_propagate_gate_update accepts. */
+#define KF_MAX_CANDIDATES 64
+
+/*
+ * kf_propagate_gate_update -- the filter with hit selection: every layer
+ * holds n_cand candidate hits per track instead of one; after the
+ * propagation each candidate gets the chi-square r^T S^-1 r that an update
+ * with it would add (r = m - H q, S = H P H^T + V, H = [I3|0]), and the
+ * candidate with the smallest one not above chi2_gate (the first of equal
+ * ones) updates the state -- the search step of track finding that runs
+ * between propagation and update (Sec. 3.1; the paper's benchmark gives each
+ * layer one hit).  If no candidate qualifies the layer is a hole: the state
+ * is the prediction and no chi-square is added.  A candidate with non-finite
+ * values or an S that is not positive definite takes no part (it does not
+ * fail the track).
+ *
+ *   geometry      0: planes z = layers[l], 1: cylinders r = layers[l]
+ *   par_in .. cov_out, layers, n_layers, n_layers_per_track, n_tracks,
+ *   bz_tesla, layout, chi2_out, status_out, tune   as in kf_propagate_update_z
+ *                 (the status word counts the layers processed, holes
+ *                 included; failures as there)
+ *   cand_pos      per layer 3 * n_cand floats per track in `layout`
+ *                 (candidate j's x, y, z at elements 3j .. 3j+2), i.e. an
+ *                 array of E = 3 n_cand elements and n_layers layers
+ *   cand_cov      per layer 6 * n_cand floats (candidate j's packed 3x3
+ *                 covariance at elements 6j .. 6j+5)
+ *   n_cand        1 .. KF_MAX_CANDIDATES
+ *   chi2_gate     the largest chi-square accepted (+inf: no gate; NaN is
+ *                 KF_E_SHAPE)
+ *   flags         0 (FP32 update)
+ *   chosen_out    [n_layers][n_tracks] int32 or NULL: the candidate used on
+ *                 each layer processed, -1 for a hole (layers not processed
+ *                 are left untouched)
+ * Errors: KF_E_SHAPE, KF_E_LAYOUT, KF_E_FLAGS, KF_E_NULL, KF_E_ALIGN,
+ * KF_E_DEVICE, KF_E_LAUNCH; nothing is enqueued on error.
+ */
+kf_status_t kf_propagate_gate_update(int32_t geometry, const float* par_in, const float* cov_in, float* par_out,
+                                     float* cov_out, const float* cand_pos, const float* cand_cov, int32_t n_cand,
+                                     float chi2_gate, const float* layers, int32_t n_layers,
+                                     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla,
+                                     kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out,
+                                     int32_t* chosen_out, const kf_tune_t* tune, void* stream);
 
 /*
  * kf_smooth -- Rauch-Tung-Striebel smoother after the filter: the backward

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkf.so")
-SOURCES = ["kf_api.hip", "kf_step.hip", "kf_batched.hip", "kf_adjoint.hip", "kf_host.hip", "kf_smooth.hip"]
+SOURCES = ["kf_api.hip", "kf_step.hip", "kf_batched.hip", "kf_adjoint.hip", "kf_host.hip", "kf_smooth.hip", "kf_gate.hip"]
 HEADERS = ["kf_device.h", "kf_internal.h", "kf_lanes.h", "kf_track.h", "kf_batched.h", "kf_dual.h", "kf_host.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

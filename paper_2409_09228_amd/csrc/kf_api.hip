@@ -309,6 +309,54 @@ kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out,
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 
+kf_status_t kf_propagate_gate_update(int32_t geometry, const float* par_in, const float* cov_in, float* par_out,
+                                     float* cov_out, const float* cand_pos, const float* cand_cov, int32_t n_cand,
+                                     float chi2_gate, const float* layers, int32_t n_layers,
+                                     const int32_t* n_layers_per_track, int64_t n_tracks, float bz_tesla,
+                                     kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out,
+                                     int32_t* chosen_out, const kf_tune_t* tune, void* stream) {
+  if (geometry != 0 && geometry != 1) return KF_E_SHAPE;
+  if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
+  if (n_cand < 1 || n_cand > KF_MAX_CANDIDATES || chi2_gate != chi2_gate) return KF_E_SHAPE;
+  kf::TrackLayout tl;
+  if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
+  if (flags != 0) return KF_E_FLAGS;
+  int block = 256;
+  if (tune) {
+    block = tune->block_threads;
+    if (block != 64 && block != 128 && block != 256) return KF_E_FLAGS;
+  }
+  if (n_tracks == 0) return KF_OK;
+  if (!par_in || !cov_in || !par_out || !cov_out) return KF_E_NULL;
+  if (n_layers > 0 && (!cand_pos || !cand_cov || !layers)) return KF_E_NULL;
+  const void* ptrs[] = {par_in, cov_in, par_out, cov_out, cand_pos, cand_cov, n_layers_per_track, chi2_out,
+                        status_out, chosen_out};
+  for (const void* p : ptrs)
+    if (p && !aligned4(p)) return KF_E_ALIGN;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  kf::GateArgs a;
+  a.par_in = par_in;
+  a.cov_in = cov_in;
+  a.par_out = par_out;
+  a.cov_out = cov_out;
+  a.cand_pos = cand_pos;
+  a.cand_cov = cand_cov;
+  a.nlay = n_layers_per_track;
+  a.chi2 = chi2_out;
+  a.status = status_out;
+  a.chosen = chosen_out;
+  a.n = n_tracks;
+  a.L = n_layers;
+  a.M = n_cand;
+  a.lay = tl;
+  a.b = float(kCLight * double(bz_tesla));
+  a.gate = chi2_gate;
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
+  const hipError_t e = kf::launch_gate(geometry, block, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
 int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_every, kf_layout_t layout) {
   kf::TrackLayout tl;
   const int sh = ckpt_shift(ckpt_every);

@@ -1,0 +1,191 @@
+// Filter with hit selection: on every layer a track has several candidate
+// hits; after the propagation each candidate gets the chi-square a Kalman
+// update with it would add, and the candidate with the smallest chi-square
+// not above the gate updates the state (the search step of track finding
+// that the paper's benchmark leaves out between propagation and update,
+// Sec. 3.1).  No qualifying candidate: the layer is a hole and the state is
+// the prediction.  A candidate with non-finite values or a residual
+// covariance that is not positive definite takes no part.
+//
+// One lane per track, the state in registers across its layers (as in the
+// plain step); per layer the lane streams its candidates (9 floats each),
+// keeping the best one's hit in registers, then runs the ordinary update
+// with it.  The decision's chi-square is computed with the same expressions
+// as the update's, so the chi-square that decides is the one that is added.
+#include "kf_device.h"
+#include "kf_internal.h"
+#include "kf_lanes.h"
+
+namespace kf {
+
+namespace {
+
+// Chi-square of an update of the prediction (q, Pt) with hit (m, V), and
+// whether the candidate takes part (finite, residual covariance positive
+// definite).  The arithmetic is update_f32's.
+__device__ __forceinline__ bool candidate_chi2(const float q[6], const float Pt[21], const float m[3],
+                                               const float V[6], float& chi2) {
+  const float r0 = m[0] - q[0], r1 = m[1] - q[1], r2 = m[2] - q[2];
+  const float S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
+  const float S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
+  const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
+  const float c00 = S11 * S22 - S21 * S21;
+  const float c10 = S20 * S21 - S10 * S22;
+  const float c11 = S00 * S22 - S20 * S20;
+  const float c20 = S10 * S21 - S11 * S20;
+  const float c21 = S10 * S20 - S00 * S21;
+  const float c22 = S00 * S11 - S10 * S10;
+  const float det = S00 * c00 + S10 * c10 + S20 * c20;
+  const bool pd = (S00 > 0.0f) & (c22 > 0.0f) & (det > 0.0f);
+  const float rdet = rcp_t(det);
+  const float i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
+  const float i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
+  const float t0 = i00 * r0 + i10 * r1 + i20 * r2;
+  const float t1 = i10 * r0 + i11 * r1 + i21 * r2;
+  const float t2 = i20 * r0 + i21 * r1 + i22 * r2;
+  chi2 = r0 * t0 + r1 * t1 + r2 * t2;
+  return in_ok & pd & fin(chi2);
+}
+
+template <int KIND, bool WIDE>
+struct Candidates {
+  const GateArgs& a;
+  const Lanes<KIND, WIDE>& ln;
+  LaneRef<WIDE> pos, cov;
+  int Ep, Ec;
+  __device__ __forceinline__ Candidates(const GateArgs& a_, const Lanes<KIND, WIDE>& ln_, int64_t i)
+      : a(a_), ln(ln_), Ep(3 * a_.M), Ec(6 * a_.M) {
+    pos = lane_ref<KIND, WIDE>(i, a.n, Ep, a.L, a.lay);
+    cov = lane_ref<KIND, WIDE>(i, a.n, Ec, a.L, a.lay);
+  }
+  // candidate j of layer k (both wave-uniform)
+  __device__ __forceinline__ void load(int k, int j, float m[3], float V[6]) const {
+    if constexpr (!WIDE) {
+      const __amdgpu_buffer_rsrc_t rp = buf_rsrc(a.cand_pos, pos.bytes);
+      const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cand_cov, cov.bytes);
+      if (KIND == KF_AOS) {
+        buf_ld_rec<3>(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j)) * 4u, m);
+        buf_ld_rec<6>(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j)) * 4u, V);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 3; ++e) m[e] = buf_ld(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j + e)) * 4u);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) V[e] = buf_ld(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j + e)) * 4u);
+      }
+    } else if (KIND == KF_AOS) {
+      ld_rec<3>(pos.at(a.cand_pos, ln.uni(Ep, k, 3 * j)), m);
+      ld_rec<6>(cov.at(a.cand_cov, ln.uni(Ec, k, 6 * j)), V);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) m[e] = *pos.at(a.cand_pos, ln.uni(Ep, k, 3 * j + e));
+#pragma unroll
+      for (int e = 0; e < 6; ++e) V[e] = *cov.at(a.cand_cov, ln.uni(Ec, k, 6 * j + e));
+    }
+  }
+};
+
+// One layer: propagate, select, update.  Returns status bits; on success
+// (p, C, d) hold the new state and `best` the candidate used (-1: a hole).
+template <int GEOM, bool ZIN, int KIND, bool WIDE>
+__device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE>& cands, int k, float p[6], float C[21],
+                                               DirT<float>& d, float& chi2, int& best) {
+  float q[6], Pt[21];
+  DirT<float> dq = d;
+  const uint32_t fp = propagate<GEOM, ZIN, float>(p, C, dq, cands.a.layer[k], cands.a.b, q, Pt);
+  bool fin_ok = true;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) fin_ok = fin_ok & fin(q[e]);
+#pragma unroll
+  for (int e = 0; e < 21; ++e) fin_ok = fin_ok & fin(Pt[e]);
+  if (fp) return fp;
+  if (!fin_ok) return S_NONFINITE;
+  best = -1;
+  float bchi = __builtin_inff();
+  float mb[3] = {0.0f, 0.0f, 0.0f}, Vb[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for (int j = 0; j < cands.a.M; ++j) {
+    float m[3], V[6], c;
+    cands.load(k, j, m, V);
+    const bool take = candidate_chi2(q, Pt, m, V, c) & (c <= cands.a.gate) & (c < bchi);
+    best = take ? j : best;
+    bchi = take ? c : bchi;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) mb[e] = take ? m[e] : mb[e];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) Vb[e] = take ? V[e] : Vb[e];
+  }
+  if (best >= 0) {
+    const float phi = q[4], theta = q[5];
+    float dchi;
+    const uint32_t fu = update<GEOM, PREC_F32, float>(q, Pt, mb, Vb, dchi);
+    if (fu) return fu;
+    rotate_by(dq.sp, dq.cp, q[4] - phi, q[4]);
+    rotate_by(dq.st, dq.ct, q[5] - theta, q[5]);
+    chi2 += dchi;
+  }
+#pragma unroll
+  for (int e = 0; e < 6; ++e) p[e] = q[e];
+#pragma unroll
+  for (int e = 0; e < 21; ++e) C[e] = Pt[e];
+  d = dq;
+  return 0u;
+}
+
+}  // namespace
+
+template <int GEOM, int KIND, bool WIDE>
+__global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
+  const Candidates<KIND, WIDE> cands(a, ln, i);
+  int nl = a.nlay ? a.nlay[i] : a.L;
+  nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
+  float p[6], C[21];
+  ln.template ld_all<6>(ln.par, a.par_in, 0, p);
+  ln.template ld_all<21>(ln.cov, a.cov_in, 0, C);
+  uint32_t flags = 0;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) flags |= fin(p[e]) ? 0u : S_NONFINITE;
+#pragma unroll
+  for (int e = 0; e < 21; ++e) flags |= fin(C[e]) ? 0u : S_NONFINITE;
+  float chi2 = 0.0f;
+  int done = 0;
+  DirT<float> d;
+  dir_init(p, d);
+  for (int k = 0; k < nl && !flags; ++k) {
+    int best = -1;
+    const uint32_t f = (GEOM == 0 && k > 0) ? gate_layer<GEOM, true>(cands, k, p, C, d, chi2, best)
+                                            : gate_layer<GEOM, false>(cands, k, p, C, d, chi2, best);
+    if (f) {
+      flags = f;
+      break;
+    }
+    if (a.chosen) a.chosen[int64_t(k) * a.n + i] = best;
+    done = k + 1;
+  }
+  ln.template st_all<6>(ln.par, a.par_out, 0, p);
+  ln.template st_all<21>(ln.cov, a.cov_out, 0, C);
+  if (a.chi2) a.chi2[i] = chi2;
+  if (a.status) a.status[i] = int32_t(flags | (uint32_t(done) << 16));
+}
+
+template <int GEOM, bool WIDE>
+static hipError_t launch_kind(int block, const GateArgs& a, hipStream_t s) {
+  const dim3 grid(unsigned((a.n + block - 1) / block));
+  if (a.lay.kind == KF_AOS)
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOS, WIDE>), grid, dim3(block), 0, s, a);
+  else if (a.lay.kind == KF_AOSOA)
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE>), grid, dim3(block), 0, s, a);
+  else
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE>), grid, dim3(block), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_gate(int geom, int block, const GateArgs& a, hipStream_t s) {
+  // 64-bit addressing once any array reaches 4 GiB (the candidates' covariances are the largest)
+  const bool wide = layout_floats(a.n, 6 * a.M, a.L, a.lay) * 4 >= (int64_t(1) << 32) || needs_wide(a.n, a.L, a.lay);
+  if (geom == 0) return wide ? launch_kind<0, true>(block, a, s) : launch_kind<0, false>(block, a, s);
+  return wide ? launch_kind<1, true>(block, a, s) : launch_kind<1, false>(block, a, s);
+}
+
+}  // namespace kf

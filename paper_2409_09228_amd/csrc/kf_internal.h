@@ -78,6 +78,29 @@ struct SmoothArgs {
 
 hipError_t launch_smooth(int geom, int block, const SmoothArgs& a, hipStream_t s);
 
+// Filter with hit selection among n_cand candidates per layer (kf_gate.hip).
+struct GateArgs {
+  const float* par_in;
+  const float* cov_in;
+  float* par_out;
+  float* cov_out;
+  const float* cand_pos;  // per layer 3 * M floats per track, in `lay`
+  const float* cand_cov;  // per layer 6 * M floats per track, in `lay`
+  const int32_t* nlay;
+  float* chi2;
+  int32_t* status;
+  int32_t* chosen;        // [L][n] or NULL
+  int64_t n;
+  int32_t L;
+  int32_t M;
+  TrackLayout lay;
+  float b;
+  float gate;
+  float layer[KF_MAX_LAYERS];
+};
+
+hipError_t launch_gate(int geom, int block, const GateArgs& a, hipStream_t s);
+
 // precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
 hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);
 // The FP64 form: FP64 arrays, FP64 arithmetic throughout (prec 0 plain update,

@@ -150,6 +150,25 @@ struct LaneRef {
   }
 };
 
+// This lane's reference into an array of E floats per track and layer, Lx
+// layers, in `lay` (for arrays whose element count is known only at run
+// time; accesses then use Lanes::uni(E, l, e)).
+template <int KIND, bool WIDE>
+__device__ __forceinline__ LaneRef<WIDE> lane_ref(int64_t i, int64_t n, int E, int Lx, TrackLayout lay) {
+  using Off = typename LaneRef<WIDE>::Off;
+  LaneRef<WIDE> r;
+  if (KIND == KF_AOSOA) {
+    const int64_t B = int64_t(1) << lay.shift;
+    r.boff = Off(((i >> lay.shift) * E * Lx * B + (i & (B - 1))) * 4);
+  } else if (KIND == KF_AOS) {
+    r.boff = Off(i * E * 4);
+  } else {
+    r.boff = Off(i * 4);
+  }
+  r.bytes = WIDE ? 0u : uint32_t(layout_floats(n, E, Lx, lay) * 4);
+  return r;
+}
+
 // SZ: bytes per element (4, or 8 for the FP64 form, which addresses with
 // 64-bit pointers: the buffer form above moves dwords only)
 template <int KIND, bool WIDE, int SZ = 4>

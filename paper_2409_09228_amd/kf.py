@@ -99,6 +99,9 @@ def lib():
         L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
         L.kf_smooth.argtypes = [i32, vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, ctypes.POINTER(Tune), vp]
         L.kf_smooth.restype = ctypes.c_int
+        L.kf_propagate_gate_update.argtypes = [i32, vp, vp, vp, vp, vp, vp, i32, f32, vp, i32, vp, i64, f32, Layout,
+                                               ctypes.c_uint32, vp, vp, vp, ctypes.POINTER(Tune), vp]
+        L.kf_propagate_gate_update.restype = ctypes.c_int
         d64 = ctypes.c_double
         for name in ("kf_propagate_update_z_f64", "kf_propagate_update_r_f64"):
             fn = getattr(L, name)
@@ -637,6 +640,46 @@ def smoothed_to_logical(st: dict, sm):
     if st["L"] == 1:
         a = a[None]
     return a[..., :6], a[..., 6:]
+
+
+def stage_candidates(st: dict, mh: dict) -> dict:
+    """Candidate hits (synth.multi_hit: cand_pos [L, n, M, 3], cand_cov
+    [L, n, M, 6]) as float32 device arrays in the staged sample's layout."""
+    import torch
+    L, n, M = mh["cand_pos"].shape[:3]
+    dev = st["par"].device
+    up = lambda a, E: torch.from_numpy(to_layout_np(np.asarray(a, np.float32).reshape(L, n, E), st["layout"])).to(dev)
+    return {"M": M, "cand_pos": up(mh["cand_pos"], 3 * M), "cand_cov": up(mh["cand_cov"], 6 * M)}
+
+
+class GateLauncher:
+    """A kf_propagate_gate_update call on a staged sample and its staged
+    candidates, every argument converted once; outputs allocated here."""
+
+    def __init__(self, st: dict, cands: dict, gate: float, tune=None, stream=None, chosen=True):
+        import torch
+        _require_cuda(st["par"], st["cov"], cands["cand_pos"], cands["cand_cov"], st["nlay"])
+        dev = st["par"].device
+        n, L = st["n"], st["L"]
+        self.par_out, self.cov_out = torch.empty_like(st["par"]), torch.empty_like(st["cov"])
+        self.chi2 = torch.empty(n, dtype=torch.float32, device=dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=dev)
+        self.chosen = torch.full((max(L, 1), n), -2, dtype=torch.int32, device=dev) if chosen else None
+        self._keep = (st, cands)
+        self._layers = np.ascontiguousarray(st["layers"], np.float32)
+        self._tune = None if tune is None else make_tune(tune)
+        with torch.cuda.device(dev):
+            sp = _stream(stream)
+        self._args = (int(st["geom"]), _ptr(st["par"]), _ptr(st["cov"]), _ptr(self.par_out), _ptr(self.cov_out),
+                      _ptr(cands["cand_pos"]), _ptr(cands["cand_cov"]), int(cands["M"]), float(gate),
+                      self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]), _ptr(st["nlay"]),
+                      int(n), float(st["bz"]), Layout(*st["layout"]), 0, _ptr(self.chi2), _ptr(self.status),
+                      _ptr(self.chosen), None if self._tune is None else ctypes.byref(self._tune), sp)
+
+    def __call__(self):
+        rc = lib().kf_propagate_gate_update(*self._args)
+        if rc != KF_OK:
+            raise KFError(rc, "kf_propagate_gate_update")
 
 
 def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,

@@ -26,7 +26,7 @@ def test_exports_every_declared_function():
 
 
 def test_version_and_strings():
-    assert K.lib().kf_abi_version() == 6
+    assert K.lib().kf_abi_version() == 7
     assert K.status_string(0) == "ok"
     assert "layout" in K.status_string(3)
 
@@ -143,3 +143,29 @@ def test_smooth_validation_before_any_device_call():
     assert call(out=ctypes.c_void_p(4097)) == 4
     assert call(n=0) == 0
     assert call(L=0) == 0
+
+
+def test_gate_validation_before_any_device_call():
+    lib = K.lib()
+    layers = (ctypes.c_float * 4)(10, 15, 20, 25)
+    h = ctypes.c_void_p(4096)
+
+    def call(geom=0, n=10, L=3, M=4, gate=30.0, layout=K.SOA, flags=0, par=h, cand=h, tune=None):
+        tn = None if tune is None else ctypes.byref(K.Tune(*tune))
+        return lib.kf_propagate_gate_update(geom, par, h, h, h, cand, h, M, gate,
+                                            ctypes.cast(layers, ctypes.c_void_p), L, None, n, 3.8,
+                                            K.Layout(*layout), flags, None, None, None, tn, None)
+    assert call(geom=3) == 2
+    assert call(n=-1) == 2
+    assert call(L=65) == 2
+    assert call(M=0) == 2
+    assert call(M=65) == 2
+    assert call(gate=float("nan")) == 2
+    assert call(layout=(1, 12)) == 3
+    assert call(flags=1) == 8
+    assert call(tune=(512, 1)) == 8
+    assert call(par=None) == 1
+    assert call(cand=None) == 1
+    assert call(cand=ctypes.c_void_p(4098)) == 4
+    assert call(n=0) == 0
+    assert call(gate=float("inf"), n=0) == 0
