@@ -608,7 +608,8 @@ def main(argv=None):
     roof["hbm_algorithmic_bytes_per_launch"] = int(bytes_)
     roof["hbm_achieved_GBs"] = round(hbm, 1)
     roof["hbm_frac"] = round(fr_hbm, 4)
-    roof["kernel"] = "kf_step_kernel<%d,%d,%s>" % (geom, {0: 0, 1: 1, 3: 2}.get(args.flags, 0), args.layout)
+    roof["kernel"] = "kf_step_kernel<%d,%d,%s,%s>" % (geom, {0: 0, 1: 1, 3: 2}.get(args.flags, 0), args.layout,
+                                                   "streamed" if st["nlay"] is None else "counted")
     roof["kernel_source_sha256"] = kernel_source_digest()
 
     out = {

@@ -138,7 +138,11 @@ enum {
  *   layer_z           HOST [n_layers], plane positions in cm
  *   n_layers          0 .. KF_MAX_LAYERS
  *   n_layers_per_track  [n_tracks] int32 or NULL: track i uses its first
- *                     min(max(n,0), n_layers) layers (NULL: all n_layers)
+ *                     min(max(n,0), n_layers) layers (NULL: all n_layers).
+ *                     With NULL every staged hit is read exactly once and
+ *                     the SoA / AoSoA kernels stream the hits with the
+ *                     non-temporal cache hint; pass NULL rather than an
+ *                     array of n_layers for the fastest form.
  *   n_tracks          >= 0 (0: nothing is enqueued)
  *   bz_tesla          uniform solenoid field
  *   flags             0 (FP32 throughout) or KF_F_* bits

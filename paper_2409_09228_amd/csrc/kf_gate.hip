@@ -47,13 +47,18 @@ __device__ __forceinline__ bool candidate_chi2(const float q[6], const float Pt[
   return in_ok & pd & fin(chi2);
 }
 
+// Candidate arrays, the state and the outputs are each moved once.
+template <int KIND, bool WIDE>
+using GateLanes = Lanes<KIND, WIDE, 4, once_policy<KIND>()>;
+
 template <int KIND, bool WIDE>
 struct Candidates {
+  static constexpr int P = once_policy<KIND>();
   const GateArgs& a;
-  const Lanes<KIND, WIDE>& ln;
+  const GateLanes<KIND, WIDE>& ln;
   LaneRef<WIDE> pos, cov;
   int Ep, Ec;
-  __device__ __forceinline__ Candidates(const GateArgs& a_, const Lanes<KIND, WIDE>& ln_, int64_t i)
+  __device__ __forceinline__ Candidates(const GateArgs& a_, const GateLanes<KIND, WIDE>& ln_, int64_t i)
       : a(a_), ln(ln_), Ep(3 * a_.M), Ec(6 * a_.M) {
     pos = lane_ref<KIND, WIDE>(i, a.n, Ep, a.L, a.lay);
     cov = lane_ref<KIND, WIDE>(i, a.n, Ec, a.L, a.lay);
@@ -64,13 +69,13 @@ struct Candidates {
       const __amdgpu_buffer_rsrc_t rp = buf_rsrc(a.cand_pos, pos.bytes);
       const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cand_cov, cov.bytes);
       if (KIND == KF_AOS) {
-        buf_ld_rec<3>(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j)) * 4u, m);
-        buf_ld_rec<6>(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j)) * 4u, V);
+        buf_ld_rec<3, P>(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j)) * 4u, m);
+        buf_ld_rec<6, P>(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j)) * 4u, V);
       } else {
 #pragma unroll
-        for (int e = 0; e < 3; ++e) m[e] = buf_ld(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j + e)) * 4u);
+        for (int e = 0; e < 3; ++e) m[e] = buf_ld<P>(rp, pos.boff, uint32_t(ln.uni(Ep, k, 3 * j + e)) * 4u);
 #pragma unroll
-        for (int e = 0; e < 6; ++e) V[e] = buf_ld(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j + e)) * 4u);
+        for (int e = 0; e < 6; ++e) V[e] = buf_ld<P>(rc, cov.boff, uint32_t(ln.uni(Ec, k, 6 * j + e)) * 4u);
       }
     } else if (KIND == KF_AOS) {
       ld_rec<3>(pos.at(a.cand_pos, ln.uni(Ep, k, 3 * j)), m);
@@ -136,7 +141,7 @@ template <int GEOM, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
+  const GateLanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
   const Candidates<KIND, WIDE> cands(a, ln, i);
   int nl = a.nlay ? a.nlay[i] : a.L;
   nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);

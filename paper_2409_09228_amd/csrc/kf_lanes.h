@@ -68,17 +68,30 @@ __device__ __forceinline__ void st_rec(T* p, const T* src) {
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void gbl_void;
 
+// Cache-policy bits of an access: 0 the default, kStreamPolicy the
+// non-temporal hint (gfx950 NT) for data that is read or written once.
+constexpr int kStreamPolicy = 2;
+// The policy for arrays a kernel reads or writes once, by layout: element-
+// major layouts (SoA, AoSoA) stream; an AoS record is moved by several
+// loads that touch the same cache lines, so it keeps the default.
+template <int KIND>
+__host__ __device__ constexpr int once_policy() {
+  return KIND == KF_AOS ? 0 : kStreamPolicy;
+}
+
 // Buffer-resource word 3 for untyped 32-bit access on gfx9-family parts.
 constexpr int kBufWord3 = 0x00020000;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, int(bytes), kBufWord3);
 }
+template <int POLICY = 0>
 __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), POLICY));
 }
+template <int POLICY = 0>
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, int(voff), int(soff), POLICY);
 }
 // Element j of a vector of dwords as a float.  The element is copied to a
 // scalar first: a bit cast applied directly to a vector subscript reads
@@ -89,49 +102,49 @@ __device__ __forceinline__ float lane_word(const V& v, int j) {
   return __builtin_bit_cast(float, w);
 }
 // N consecutive floats of one lane: dwordx4 pieces, then x3/x2/x1 for the rest
-template <int N>
+template <int N, int POLICY = 0>
 __device__ __forceinline__ void buf_ld_rec(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float* dst) {
 #pragma unroll
   for (int c = 0; c + 4 <= N; c += 4) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff + 4 * c), 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, int(voff), int(soff + 4 * c), POLICY);
 #pragma unroll
     for (int j = 0; j < 4; ++j) dst[c + j] = lane_word(v, j);
   }
   constexpr int c = N & ~3;
   if (N - c == 3) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff + 4 * c), 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, int(voff), int(soff + 4 * c), POLICY);
 #pragma unroll
     for (int j = 0; j < 3; ++j) dst[c + j] = lane_word(v, j);
   } else if (N - c == 2) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff + 4 * c), 0);
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff + 4 * c), POLICY);
     dst[c] = lane_word(v, 0);
     dst[c + 1] = lane_word(v, 1);
   } else if (N - c == 1) {
-    dst[c] = buf_ld(r, voff, soff + 4 * c);
+    dst[c] = buf_ld<POLICY>(r, voff, soff + 4 * c);
   }
 }
-template <int N>
+template <int N, int POLICY = 0>
 __device__ __forceinline__ void buf_st_rec(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, const float* src) {
 #pragma unroll
   for (int c = 0; c + 4 <= N; c += 4) {
     __attribute__((ext_vector_type(4))) unsigned v;
 #pragma unroll
     for (int j = 0; j < 4; ++j) v[j] = __builtin_bit_cast(unsigned, src[c + j]);
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, int(voff), int(soff + 4 * c), 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, int(voff), int(soff + 4 * c), POLICY);
   }
   constexpr int c = N & ~3;
   if (N - c == 3) {
     __attribute__((ext_vector_type(3))) unsigned v;
 #pragma unroll
     for (int j = 0; j < 3; ++j) v[j] = __builtin_bit_cast(unsigned, src[c + j]);
-    __builtin_amdgcn_raw_buffer_store_b96(v, r, int(voff), int(soff + 4 * c), 0);
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, int(voff), int(soff + 4 * c), POLICY);
   } else if (N - c == 2) {
     __attribute__((ext_vector_type(2))) unsigned v;
     v[0] = __builtin_bit_cast(unsigned, src[c]);
     v[1] = __builtin_bit_cast(unsigned, src[c + 1]);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), int(soff + 4 * c), 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), int(soff + 4 * c), POLICY);
   } else if (N - c == 1) {
-    buf_st(r, voff, soff + 4 * c, src[c]);
+    buf_st<POLICY>(r, voff, soff + 4 * c, src[c]);
   }
 }
 
@@ -170,8 +183,9 @@ __device__ __forceinline__ LaneRef<WIDE> lane_ref(int64_t i, int64_t n, int E, i
 }
 
 // SZ: bytes per element (4, or 8 for the FP64 form, which addresses with
-// 64-bit pointers: the buffer form above moves dwords only)
-template <int KIND, bool WIDE, int SZ = 4>
+// 64-bit pointers: the buffer form above moves dwords only).  POL: the cache
+// policy of ld_all / ld_first / st_all in the buffer form.
+template <int KIND, bool WIDE, int SZ = 4, int POL = 0>
 struct Lanes {
   static_assert(SZ == 4 || (SZ == 8 && WIDE), "FP64 arrays use the 64-bit address form");
   LaneRef<WIDE> par, cov, hp, hc, ck;
@@ -215,10 +229,10 @@ struct Lanes {
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {
-        buf_ld_rec<E>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
+        buf_ld_rec<E, POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
       } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) dst[e] = buf_ld(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
+        for (int e = 0; e < E; ++e) dst[e] = buf_ld<POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
       }
     } else if (KIND == KF_AOS) {
       ld_rec<E>(r.at(base, uni(E, l, 0)), dst);
@@ -234,10 +248,10 @@ struct Lanes {
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {
-        buf_ld_rec<N>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
+        buf_ld_rec<N, POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, dst);
       } else {
 #pragma unroll
-        for (int e = 0; e < N; ++e) dst[e] = buf_ld(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
+        for (int e = 0; e < N; ++e) dst[e] = buf_ld<POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u);
       }
     } else if (KIND == KF_AOS) {
       ld_rec<N>(r.at(base, uni(E, l, 0)), dst);
@@ -252,10 +266,10 @@ struct Lanes {
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {
-        buf_st_rec<E>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, src);
+        buf_st_rec<E, POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, src);
       } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) buf_st(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u, src[e]);
+        for (int e = 0; e < E; ++e) buf_st<POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u, src[e]);
       }
     } else if (KIND == KF_AOS) {
       st_rec<E>(r.at(base, uni(E, l, 0)), src);
@@ -269,8 +283,8 @@ struct Lanes {
   // layer is min(j_uni, the lane's last layer): j_uni is wave-uniform and
   // <= L - 1, last_off the lane's byte offset of its last layer (layer_off).
   // Completion is tracked by the wave's vector-memory counter only; the
-  // caller waits before reading.
-  template <int E>
+  // caller waits before reading.  POLICY: the copies' cache-policy bits.
+  template <int E, int POLICY = 0>
   __device__ __forceinline__ void stage(const LaneRef<WIDE>& r, const float* base, int j_uni,
                                         typename LaneRef<WIDE>::Off last_off, float* lds) const {
     using Off = typename LaneRef<WIDE>::Off;
@@ -282,12 +296,12 @@ struct Lanes {
 #pragma unroll
       for (int e = 0; e < E; ++e)
         __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_void*)(lds + e * 64), 4, int(off), int(uint32_t(e * es * 4)),
-                                                 0, 0);
+                                                 0, POLICY);
     } else {
       const float* p = reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        __builtin_amdgcn_global_load_lds((gbl_void*)(p + e * es), (lds_void*)(lds + e * 64), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((gbl_void*)(p + e * es), (lds_void*)(lds + e * 64), 4, 0, POLICY);
     }
   }
   // byte offset of this lane's layer l (element 0) in a per-layer array of E elements

@@ -224,8 +224,12 @@ __device__ __forceinline__ void cyl_predict(const float p[6], float rk, float b,
   (void)helix_to_cylinder(p, d, rk, b, q, J, dq);
 }
 
+// Checkpoints are read once and smoothed states written once.
 template <int KIND, bool WIDE>
-__device__ __forceinline__ void store_state(const Lanes<KIND, WIDE>& ln, float* base, int k, const float p[6],
+using SmoothLanes = Lanes<KIND, WIDE, 4, once_policy<KIND>()>;
+
+template <int KIND, bool WIDE>
+__device__ __forceinline__ void store_state(const SmoothLanes<KIND, WIDE>& ln, float* base, int k, const float p[6],
                                             const float C[21]) {
   float s[27];
 #pragma unroll
@@ -241,7 +245,7 @@ template <int GEOM, int KIND, bool WIDE>
 __global__ void __launch_bounds__(256) kf_smooth_kernel(const SmoothArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.L);
+  const SmoothLanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.L);
   int nd = int(uint32_t(a.status[i]) >> 16);
   nd = nd > a.L ? a.L : nd;
   if (nd <= 0) return;

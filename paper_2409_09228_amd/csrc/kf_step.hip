@@ -50,10 +50,11 @@ struct LaidOutHits {
   static constexpr bool kStaged = KIND != KF_AOS && sizeof(T) == 4;
   __device__ __forceinline__ int next(int k) const { return k + 1 < a.L ? k + 1 : k; }
   // layer min(j, the track's last layer); j is wave-uniform
+  template <int POLICY>
   __device__ __forceinline__ void stage(int j, float* slot) const {
     const int ju = j < a.L - 1 ? j : a.L - 1;
-    ln.template stage<3>(ln.hp, a.hit_pos, ju, hp_last, slot);
-    ln.template stage<6>(ln.hc, a.hit_cov, ju, hc_last, slot + 3 * 64);
+    ln.template stage<3, POLICY>(ln.hp, a.hit_pos, ju, hp_last, slot);
+    ln.template stage<6, POLICY>(ln.hc, a.hit_cov, ju, hc_last, slot + 3 * 64);
   }
 };
 
@@ -80,8 +81,11 @@ struct LaidOutCkpt {
 #define KF_STEP_OCCUPANCY
 #endif
 
-// dynamic LDS: kRingFloats per wave of the block (layouts whose hits are staged)
-template <int GEOM, int PREC, int KIND, bool WIDE>
+// dynamic LDS: kRingFloats per wave of the block (layouts whose hits are staged).
+// STREAM: every track runs all a.L layers, so each staged hit is read once
+// (no wave re-reads the last layers of finished tracks) and the copies carry
+// the non-temporal hint.
+template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM>
 __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const StepArgs a) {
   extern __shared__ float kf_lds[];
   float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kRingFloats;
@@ -94,7 +98,7 @@ __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const St
   uint32_t status;
   const LaidOutHits<KIND, WIDE> hits(a, ln, nl);
   if constexpr (LaidOutHits<KIND, WIDE>::kStaged) {
-    LayerRing<LaidOutHits<KIND, WIDE>> stager(hits, ring);
+    LayerRing<LaidOutHits<KIND, WIDE>, STREAM ? kStreamPolicy : 0> stager(hits, ring);
     run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
                           a.layer, a.b, chi2, status);
   } else {
@@ -109,10 +113,15 @@ __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const St
 template <int GEOM, int PREC, int KIND, bool WIDE>
 static hipError_t launch_one(int block, const StepArgs& a, hipStream_t s) {
   const int64_t grid = (a.n + block - 1) / block;
-  const size_t lds = LaidOutHits<KIND, WIDE>::kStaged ? size_t(block / 64) * kRingFloats * sizeof(float) : 0;
+  constexpr bool kStaged = LaidOutHits<KIND, WIDE>::kStaged;
+  const size_t lds = kStaged ? size_t(block / 64) * kRingFloats * sizeof(float) : 0;
   // copies straight into LDS address it through the low 16 bits of M0
   static_assert(4 * kRingFloats * sizeof(float) <= 65536, "a 256-thread block's rings must lie in 64 KiB of LDS");
-  hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE>), dim3(unsigned(grid)), dim3(block), lds, s, a);
+  if (kStaged && !a.nlay)
+    hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE, kStaged>), dim3(unsigned(grid)), dim3(block), lds, s,
+                       a);
+  else
+    hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE, false>), dim3(unsigned(grid)), dim3(block), lds, s, a);
   return hipGetLastError();
 }
 

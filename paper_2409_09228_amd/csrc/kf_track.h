@@ -42,7 +42,10 @@ __device__ __forceinline__ uint32_t layer_step(T p[6], T C[21], DirT<T>& d, cons
 // without holding registers for them.  The copies go straight from memory to
 // LDS and complete in order, so reading slot k only needs the wave's
 // vector-memory counter down to the 9 (kRing - 1) copies issued after it.
-constexpr int kRing = 3;
+#ifndef KF_RING
+#define KF_RING 3  // build option: layers of hits in flight per wave
+#endif
+constexpr int kRing = KF_RING;
 constexpr int kSlotFloats = 9 * 64;
 constexpr int kRingFloats = kRing * kSlotFloats;  // per wave
 
@@ -100,9 +103,10 @@ struct RegStager {
 };
 
 // Element-major hits through this wave's LDS ring (kRingFloats at `ring`).
-// hits.stage(j, slot): start copying the hit of layer min(j, the track's last
-// layer) into the slot (j wave-uniform).
-template <class Hits>
+// hits.stage<POLICY>(j, slot): start copying the hit of layer min(j, the
+// track's last layer) into the slot (j wave-uniform), with cache policy
+// POLICY.
+template <class Hits, int POLICY = 0>
 struct LayerRing {
   static constexpr bool kCooperative = false;
   const Hits& h;
@@ -111,14 +115,14 @@ struct LayerRing {
   __device__ __forceinline__ LayerRing(const Hits& h_, float* ring_) : h(h_), ring(ring_), s(0) {}
   __device__ __forceinline__ void begin() {
 #pragma unroll
-    for (int i = 0; i < kRing; ++i) h.stage(i, ring + i * kSlotFloats);
+    for (int i = 0; i < kRing; ++i) h.template stage<POLICY>(i, ring + i * kSlotFloats);
   }
   __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
     float* slot = ring + s * kSlotFloats;
     wait_vmem<9 * (kRing - 1)>();
     read_slot(slot, int(threadIdx.x & 63), m, V);
     wait_lds();
-    h.stage(k + kRing, slot);
+    h.template stage<POLICY>(k + kRing, slot);
     s = s + 1 == kRing ? 0 : s + 1;
   }
   __device__ __forceinline__ void end() { wait_vmem<0>(); }

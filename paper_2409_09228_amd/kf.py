@@ -310,6 +310,17 @@ def from_soa_tensor(t) -> np.ndarray:
     return np.ascontiguousarray(a.T if a.ndim == 2 else a.transpose(0, 2, 1))
 
 
+def stage_nlay(nlay, L: int, device="cuda"):
+    """Per-track layer counts as a device tensor, or None when every track
+    runs all L layers: the library then knows that each staged hit is read
+    once and streams the hits (non-temporal cache hint)."""
+    import torch
+    nl = np.ascontiguousarray(nlay, np.int32)
+    if nl.size and np.all(nl == L):
+        return None
+    return torch.from_numpy(nl).to(device)
+
+
 def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
     """Upload a synthetic sample (single geometry) as float32 device tensors in `layout`."""
     import torch
@@ -321,8 +332,7 @@ def stage_sample(sample: dict, layout=SOA, device="cuda") -> dict:
         "hit_pos": to_soa_tensor(sample["hit_pos"], device),
         "hit_cov": to_soa_tensor(sample["hit_cov"], device),
     }
-    out = {"n": n, "L": L, "layout": layout, "bz": float(sample["bz"]),
-           "nlay": torch.from_numpy(np.ascontiguousarray(sample["nlay"], np.int32)).to(device)}
+    out = {"n": n, "L": L, "layout": layout, "bz": float(sample["bz"]), "nlay": stage_nlay(sample["nlay"], L, device)}
     geom = int(sample["geom"][0]) if n else 0
     out["geom"] = geom
     out["layers"] = np.asarray(sample["layer_z"] if geom == 0 else sample["layer_r"], np.float32)[:L]
@@ -448,6 +458,8 @@ def stage_host(sample: dict, layout=SOA, pinned: bool = True) -> dict:
     torch.cuda.synchronize()
     out = dict(st)
     for k in ("par", "cov", "hit_pos", "hit_cov", "nlay"):
+        if st[k] is None:
+            continue
         t = st[k].cpu()
         out[k] = t.pin_memory() if pinned else t
     return out

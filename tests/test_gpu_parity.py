@@ -216,3 +216,21 @@ def test_bad_arguments_raise(kf):
         kf.run_staged(st, flags=8)
     with pytest.raises(kf.KFError):
         kf.run_staged(st, tune=(96, 1))
+
+
+@pytest.mark.parametrize("layout", ["soa", "aosoa64"])
+def test_streamed_and_counted_forms_agree_bitwise(kf, layout):
+    """Without per-track layer counts the kernels stream the hits with the
+    non-temporal cache hint; an explicit array of n_layers per track takes the
+    default form.  The arithmetic is the same: identical results."""
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(5000))
+    st = kf.stage_sample(s, _layout(kf, layout))
+    assert st["nlay"] is None
+    a = kf.run_staged(st)
+    full = torch.full((st["n"],), st["L"], dtype=torch.int32, device="cuda")
+    b = kf.run_staged(dict(st, nlay=full))
+    torch.cuda.synchronize()
+    # (AoSoA padding lanes hold no track and are written by neither)
+    for x, y in zip(kf.results_to_logical(st, a[0], a[1]), kf.results_to_logical(st, b[0], b[1])):
+        np.testing.assert_array_equal(x, y)
+    assert torch.equal(a[2], b[2]) and torch.equal(a[3], b[3])
