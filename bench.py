@@ -112,15 +112,16 @@ def cpu_baseline(sample, n_tracks: int):
 
 
 def time_launches(fn, steps: int, stream):
-    """Mean per-call GPU time (ms) of `fn` over `steps` calls after >= 300 ms of warm-up."""
+    """Mean per-call GPU time (ms) of `fn` over `steps` back-to-back calls,
+    directly after >= 500 ms of warm-up calls."""
     import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     t_w = time.perf_counter()
-    while time.perf_counter() - t_w < 0.3:
+    while time.perf_counter() - t_w < 0.5:
         for _ in range(10):
             fn()
         torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(steps):
         fn()
@@ -541,22 +542,21 @@ def main(argv=None):
                                    st["bz"], n, out=(par_out, cov_out), chi2=chi2, status=status,
                                    nlay=st["nlay"], layout=layout, flags=args.flags, tune=tune, stream=stream)
 
-    # warm-up: W steps, and at least 300 ms of GPU work so that clocks have
-    # settled before the timed region
+    # warm-up: W steps, and at least 500 ms of GPU work so that clocks have
+    # settled; the timed region follows it directly (no other GPU work or
+    # idle time in between)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     for _ in range(args.warmup):
         step_prealloc()
     torch.cuda.synchronize()
     t_w = time.perf_counter()
-    while time.perf_counter() - t_w < 0.3:
+    while time.perf_counter() - t_w < 0.5:
         for _ in range(20):
             step_prealloc()
         torch.cuda.synchronize()
-    ok = int(((status & 0xFF) == 0).sum().item())
     # timed region: K back-to-back launches between two events on the launch
     # stream; the average launch duration is the interval over K
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
@@ -567,6 +567,7 @@ def main(argv=None):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     ms_step = ms / args.steps
+    ok = int(((status & 0xFF) == 0).sum().item())
     value = updates * args.steps / (ms / 1e3)
     kernel_ms = ms_step
     # diagnostics only (not used above): per-launch spread, events between launches

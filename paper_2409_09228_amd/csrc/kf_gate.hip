@@ -47,18 +47,25 @@ __device__ __forceinline__ bool candidate_chi2(const float q[6], const float Pt[
   return in_ok & pd & fin(chi2);
 }
 
-// Candidate arrays, the state and the outputs are each moved once.
-template <int KIND, bool WIDE>
-using GateLanes = Lanes<KIND, WIDE, 4, once_policy<KIND>()>;
+// STREAM: every track runs all layers (no per-track counts), so every wave
+// reads whole rows of candidates, each once, and the state and candidate
+// arrays carry the non-temporal hint (element-major layouts); waves of
+// tracks with different layer counts read partial rows and keep the default.
+template <int KIND, bool STREAM>
+constexpr int gate_policy() {
+  return STREAM ? once_policy<KIND>() : 0;
+}
+template <int KIND, bool WIDE, bool STREAM>
+using GateLanes = Lanes<KIND, WIDE, 4, gate_policy<KIND, STREAM>()>;
 
-template <int KIND, bool WIDE>
+template <int KIND, bool WIDE, bool STREAM>
 struct Candidates {
-  static constexpr int P = once_policy<KIND>();
+  static constexpr int P = gate_policy<KIND, STREAM>();
   const GateArgs& a;
-  const GateLanes<KIND, WIDE>& ln;
+  const GateLanes<KIND, WIDE, STREAM>& ln;
   LaneRef<WIDE> pos, cov;
   int Ep, Ec;
-  __device__ __forceinline__ Candidates(const GateArgs& a_, const GateLanes<KIND, WIDE>& ln_, int64_t i)
+  __device__ __forceinline__ Candidates(const GateArgs& a_, const GateLanes<KIND, WIDE, STREAM>& ln_, int64_t i)
       : a(a_), ln(ln_), Ep(3 * a_.M), Ec(6 * a_.M) {
     pos = lane_ref<KIND, WIDE>(i, a.n, Ep, a.L, a.lay);
     cov = lane_ref<KIND, WIDE>(i, a.n, Ec, a.L, a.lay);
@@ -91,8 +98,8 @@ struct Candidates {
 
 // One layer: propagate, select, update.  Returns status bits; on success
 // (p, C, d) hold the new state and `best` the candidate used (-1: a hole).
-template <int GEOM, bool ZIN, int KIND, bool WIDE>
-__device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE>& cands, int k, float p[6], float C[21],
+template <int GEOM, bool ZIN, int KIND, bool WIDE, bool STREAM>
+__device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STREAM>& cands, int k, float p[6], float C[21],
                                                DirT<float>& d, float& chi2, int& best) {
   float q[6], Pt[21];
   DirT<float> dq = d;
@@ -137,12 +144,12 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE>& can
 
 }  // namespace
 
-template <int GEOM, int KIND, bool WIDE>
+template <int GEOM, int KIND, bool WIDE, bool STREAM>
 __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
-  const GateLanes<KIND, WIDE> ln(i, a.n, a.L, a.lay);
-  const Candidates<KIND, WIDE> cands(a, ln, i);
+  const GateLanes<KIND, WIDE, STREAM> ln(i, a.n, a.L, a.lay);
+  const Candidates<KIND, WIDE, STREAM> cands(a, ln, i);
   int nl = a.nlay ? a.nlay[i] : a.L;
   nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
   float p[6], C[21];
@@ -177,12 +184,17 @@ __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
 template <int GEOM, bool WIDE>
 static hipError_t launch_kind(int block, const GateArgs& a, hipStream_t s) {
   const dim3 grid(unsigned((a.n + block - 1) / block));
+  const bool stream = a.nlay == nullptr;
   if (a.lay.kind == KF_AOS)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOS, WIDE>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOS, WIDE, false>), grid, dim3(block), 0, s, a);
+  else if (a.lay.kind == KF_AOSOA && stream)
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE, true>), grid, dim3(block), 0, s, a);
   else if (a.lay.kind == KF_AOSOA)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE, false>), grid, dim3(block), 0, s, a);
+  else if (stream)
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE, true>), grid, dim3(block), 0, s, a);
   else
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE, false>), grid, dim3(block), 0, s, a);
   return hipGetLastError();
 }
 

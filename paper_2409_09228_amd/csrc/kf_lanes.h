@@ -260,16 +260,17 @@ struct Lanes {
       for (int e = 0; e < N; ++e) dst[e] = *r.at(base, uni(E, l, e));
     }
   }
-  template <int E, class T>
+  // P: the stores' cache policy (default: the object's)
+  template <int E, class T, int P = POL>
   __device__ __forceinline__ void st_all(const LaneRef<WIDE>& r, T* base, int l, const T* src) const {
     static_assert(sizeof(T) == SZ, "element size");
     if constexpr (!WIDE) {
       const __amdgpu_buffer_rsrc_t rs = buf_rsrc(base, r.bytes);
       if (KIND == KF_AOS) {
-        buf_st_rec<E, POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, src);
+        buf_st_rec<E, P>(rs, uint32_t(r.boff), uint32_t(uni(E, l, 0)) * 4u, src);
       } else {
 #pragma unroll
-        for (int e = 0; e < E; ++e) buf_st<POL>(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u, src[e]);
+        for (int e = 0; e < E; ++e) buf_st<P>(rs, uint32_t(r.boff), uint32_t(uni(E, l, e)) * 4u, src[e]);
       }
     } else if (KIND == KF_AOS) {
       st_rec<E>(r.at(base, uni(E, l, 0)), src);

@@ -49,6 +49,7 @@ struct LaidOutHits {
   // float layouts through LDS
   static constexpr bool kStaged = KIND != KF_AOS && sizeof(T) == 4;
   __device__ __forceinline__ int next(int k) const { return k + 1 < a.L ? k + 1 : k; }
+  __device__ __forceinline__ int n_layers() const { return a.L; }
   // layer min(j, the track's last layer); j is wave-uniform
   template <int POLICY>
   __device__ __forceinline__ void stage(int j, float* slot) const {
@@ -69,7 +70,8 @@ struct LaidOutCkpt {
     for (int e = 0; e < 6; ++e) s[e] = p[e];
 #pragma unroll
     for (int e = 0; e < 21; ++e) s[6 + e] = C[e];
-    ln.template st_all<27>(ln.ck, a.ckpt, k >> a.ck_shift, s);
+    // written once here, read back by another kernel: not kept in cache
+    ln.template st_all<27, T, once_policy<KIND>()>(ln.ck, a.ckpt, k >> a.ck_shift, s);
   }
 };
 

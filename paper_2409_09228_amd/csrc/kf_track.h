@@ -105,7 +105,10 @@ struct RegStager {
 // Element-major hits through this wave's LDS ring (kRingFloats at `ring`).
 // hits.stage<POLICY>(j, slot): start copying the hit of layer min(j, the
 // track's last layer) into the slot (j wave-uniform), with cache policy
-// POLICY.
+// POLICY.  hits.n_layers(): the layer table's length L.  Layers from L on
+// are never copied (no track has them): near the end of the table fewer
+// than kRing - 1 copies follow the slot being read, and the wait is for all
+// of them.
 template <class Hits, int POLICY = 0>
 struct LayerRing {
   static constexpr bool kCooperative = false;
@@ -115,14 +118,18 @@ struct LayerRing {
   __device__ __forceinline__ LayerRing(const Hits& h_, float* ring_) : h(h_), ring(ring_), s(0) {}
   __device__ __forceinline__ void begin() {
 #pragma unroll
-    for (int i = 0; i < kRing; ++i) h.template stage<POLICY>(i, ring + i * kSlotFloats);
+    for (int i = 0; i < kRing; ++i)
+      if (i < h.n_layers()) h.template stage<POLICY>(i, ring + i * kSlotFloats);
   }
   __device__ __forceinline__ void get(int k, float m[3], float V[6]) {
     float* slot = ring + s * kSlotFloats;
-    wait_vmem<9 * (kRing - 1)>();
+    if (k + kRing - 1 < h.n_layers())
+      wait_vmem<9 * (kRing - 1)>();
+    else
+      wait_vmem<0>();
     read_slot(slot, int(threadIdx.x & 63), m, V);
     wait_lds();
-    h.template stage<POLICY>(k + kRing, slot);
+    if (k + kRing < h.n_layers()) h.template stage<POLICY>(k + kRing, slot);
     s = s + 1 == kRing ? 0 : s + 1;
   }
   __device__ __forceinline__ void end() { wait_vmem<0>(); }

@@ -169,3 +169,23 @@ def test_full_size_sampled(kf):
     got_sub = tuple(x[idx] for x in got[:4]) + (got[4][:, idx],)
     differ = _check(kf, sub, mh_sub, got_sub, what="full size")
     assert differ < 0.01
+
+
+def test_streamed_and_counted_forms_agree_bitwise(kf):
+    """No per-track layer counts: the candidates stream with the
+    non-temporal hint; an explicit array of n_layers takes the default form.
+    Same arithmetic, identical results."""
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(4000))
+    mh = S.multi_hit(s, 8, spread=10.0)
+    st = kf.stage_sample(s, kf.SOA)
+    assert st["nlay"] is None
+    cands = kf.stage_candidates(st, mh)
+    a = kf.GateLauncher(st, cands, GATE)
+    a()
+    full = torch.full((st["n"],), st["L"], dtype=torch.int32, device="cuda")
+    b = kf.GateLauncher(dict(st, nlay=full), cands, GATE)
+    b()
+    torch.cuda.synchronize()
+    for x, y in ((a.par_out, b.par_out), (a.cov_out, b.cov_out), (a.chi2, b.chi2), (a.status, b.status),
+                 (a.chosen, b.chosen)):
+        assert torch.equal(x, y)
