@@ -120,7 +120,16 @@ def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0):
         O.run_sample(one, nthreads=1)
         r1 += 1
     d1 = time.perf_counter() - t1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": upd * reps / dt, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": model,
             "sample": f"first {len(idx)} tracks ({upd} track-layer updates) of the same sample, FP64, OpenMP "
                       f"over tracks, {reps} passes in {dt:.1f} s wall",
             "single_thread_value": u1 * r1 / d1,
