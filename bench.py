@@ -106,12 +106,15 @@ def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0):
     sub = S.subset(sample, idx)
     upd = int(sub["nlay"].sum())
     threads = len(os.sched_getaffinity(0))
-    reps = 0
+    passes = []
     t0 = time.perf_counter()
-    while reps == 0 or time.perf_counter() - t0 < min_seconds:
+    while not passes or time.perf_counter() - t0 < min_seconds:
+        tp = time.perf_counter()
         O.run_sample(sub, nthreads=threads)
-        reps += 1
+        passes.append(time.perf_counter() - tp)
+    reps = len(passes)
     dt = time.perf_counter() - t0
+    med = float(np.median(passes))
     one = S.subset(sample, idx[: max(1, len(idx) // 20)])
     u1 = int(one["nlay"].sum())
     r1 = 0
@@ -128,10 +131,11 @@ def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0):
                 break
     except OSError:
         pass
-    return {"value": upd * reps / dt, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
+    return {"value": upd / med, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
             "cpu_model": model,
             "sample": f"first {len(idx)} tracks ({upd} track-layer updates) of the same sample, FP64, OpenMP "
-                      f"over tracks, {reps} passes in {dt:.1f} s wall",
+                      f"over tracks; median of {reps} passes ({dt:.1f} s wall in all)",
+            "mean_value": upd * reps / dt,
             "single_thread_value": u1 * r1 / d1,
             "single_thread_sample": f"first {one['par'].shape[0]} tracks ({u1} updates), 1 thread, "
                                     f"{r1} passes in {d1:.1f} s"}
@@ -666,7 +670,7 @@ def main(argv=None):
         "dtype": "f32" if args.flags == 0 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "tracks": n, "layers": int(sample["hit_pos"].shape[0]),
-                   "updates_per_step": updates, "layout": args.layout, "precision_flags": args.flags,
+                   "updates_per_step": updates, "nominal_updates_per_step": n * int(sample["hit_pos"].shape[0]), "layout": args.layout, "precision_flags": args.flags,
                    "block": args.block, "tracks_per_thread": args.tpt,
                    "tracks_per_s": round(n * args.steps / (ms / 1e3), 1), "ok_tracks": ok,
                    "host_wall_s": round(wall, 4), "launch_ms_mean": round(kernel_ms, 4),
