@@ -177,7 +177,10 @@ def bench_batched(args, sample):
                  "worst_ms": round(max(t for _, t in res["tried"]), 4)}
         args.block, args.tpt, args.sched, args.waves_mult, args.layout = (c["block"], c["tpt"], c["schedule"],
                                                                           c["waves_mult"], c["layout"])
-    layout = parse_layout(args.layout) if args.layout != "soa" or args.autotune else K.AOS
+    # the batched form's default state layout is AoS (one record per track,
+    # gathered by item); an explicit --layout or the autotuner's choice wins
+    layout_name = args.layout if args.layout != "soa" or args.autotune else "aos"
+    layout = parse_layout(layout_name)
     st = K.stage_batched(sample, layout)
     n = st["n"]
     updates = int(sample["nlay"].sum())
@@ -213,6 +216,25 @@ def bench_batched(args, sample):
 
     if launches:
         ms_b = time_launches(per_bucket, max(1, args.steps // 4), stream)
+    # roofline of the whole call (planning included): algorithmic bytes are the
+    # hits (36 B per update) and per track the state in and out, chi2, status,
+    # layer count, geometry and hit offset (216 + 8 + 4 + 1 + 8 B); flops per
+    # update by geometry, transcendentals charged
+    sec = ms / 1e3
+    nl = np.asarray(sample["nlay"], np.int64)
+    g = np.asarray(sample["geom"])
+    bytes_ = LAYER_BYTES * updates + (216 + 8 + 4 + 1 + 8) * n
+    flops_c = float(sum(FLOPS_CHARGED_PER_UPDATE[k] * nl[g == k].sum() for k in (0, 1)))
+    fr_hbm = bytes_ / sec / 1e9 / HBM_PEAK_GBS
+    fr_valu = flops_c / sec / 1e12 / FP32_PEAK_TFLOPS
+    if fr_hbm >= fr_valu:
+        roof = {"bound": "hbm", "achieved": round(bytes_ / sec / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(fr_hbm, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(flops_c / sec / 1e12, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(fr_valu, 4), "traffic": None}
+    roof.update(hbm_frac=round(fr_hbm, 4), valu_frac_charged=round(fr_valu, 4),
+                hbm_algorithmic_bytes_per_launch=int(bytes_), kernel="kf_batched_kernel (+ 3 planning kernels)")
     return {
         "metric": METRIC,
         "value": round(updates / (ms / 1e3), 1),
@@ -221,12 +243,13 @@ def bench_batched(args, sample):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.flags == 0 else "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "form": "persistent batched launch, hipGraph replay",
-                   "tracks": n, "updates_per_step": updates, "state_layout": args.layout,
+                   "tracks": n, "updates_per_step": updates, "state_layout": layout_name,
                    "block": args.block, "tracks_per_thread": args.tpt, "schedule": args.sched,
                    "waves_mult": args.waves_mult, "ok_tracks": ok,
                    "per_bucket_launches": len(launches), "per_bucket_ms": round(ms_b, 4),
                    "per_bucket_updates_per_s": round(updates / (ms_b / 1e3), 1),
                    "speedup_vs_per_bucket": round(ms_b / ms, 3), "autotune": tuned},
+        "roofline": roof,
     }
 
 
