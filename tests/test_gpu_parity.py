@@ -234,3 +234,54 @@ def test_streamed_and_counted_forms_agree_bitwise(kf, layout):
     for x, y in zip(kf.results_to_logical(st, a[0], a[1]), kf.results_to_logical(st, b[0], b[1])):
         np.testing.assert_array_equal(x, y)
     assert torch.equal(a[2], b[2]) and torch.equal(a[3], b[3])
+
+
+def _ragged_with_failures(name, n, seed):
+    """n tracks of `name` with random layer counts 0..L (p2z) or the reach
+    counts (p2r), two non-finite inputs and one hit whose covariance makes S
+    indefinite part-way along a track."""
+    s = S.subset(S.generate(name, n_events=1), np.arange(n))
+    s = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in s.items()}
+    rng = np.random.default_rng(seed)
+    L = s["hit_pos"].shape[0]
+    if name.startswith("p2z"):
+        s["nlay"] = rng.integers(0, L + 1, n).astype(s["nlay"].dtype)
+    s["par"][5, 3] = np.nan
+    s["cov"][n - 2, 0] = np.inf
+    j = int(np.argmax(s["nlay"]))
+    s["hit_cov"][3, j] = (-1e3, 0.0, -1e3, 0.0, 0.0, -1e3)
+    return s, j
+
+
+@pytest.mark.parametrize("name", ["p2r_100x9600", "p2z_1x8192"])
+@pytest.mark.parametrize("layout", ["soa", "aosoa32", "aosoa128"])
+@pytest.mark.parametrize("block", [64, 128, 256])
+def test_staged_ragged_form_matches_register_form_bitwise(kf, name, layout, block):
+    """Per-track layer counts: element-major layouts stage the hits through
+    each wave's LDS ring (finished lanes re-read their last layer), AoS
+    records fetch them one layer ahead into registers.  Each track's
+    arithmetic is the same in both, so the results are identical, including
+    non-finite inputs, a track that fails part-way (recomputed up to its
+    failing layer) and the block tail."""
+    n = 5000 + block // 2 + 3
+    s, j = _ragged_with_failures(name, n, 11)
+    tune = (block, 1)
+    got = _gpu_run(kf, s, _layout(kf, layout), tune=tune)
+    ref = _gpu_run(kf, s, kf.AOS, tune=tune)
+    for x, y in zip(got, ref):
+        np.testing.assert_array_equal(x, y)
+    st = got[3]
+    assert st[5] & 1 and st[n - 2] & 1 and (st[5] >> 16) == 0
+    assert st[j] & 2 and (st[j] >> 16) == 3
+    assert ((st >> 16) <= s["nlay"]).all()
+
+
+def test_ragged_failures_against_oracle(kf):
+    """Random per-track layer counts (0..L), non-finite inputs and a part-way
+    failure on p2z, against the FP64 oracle."""
+    s, _ = _ragged_with_failures("p2z_1x8192", 3000, 12)
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    ok = ((ref[3] & 0xFF) == 0) & np.all(np.isfinite(ref[0]), 1)
+    assert_within(metrics(ref, got, 0, mask=ok), TOL_F32, "ragged p2z")
