@@ -297,6 +297,20 @@ def bench_adjoint(args, sample):
     totals["recompute"] = ms["forward_plain"] + ms["backward_recompute"]
     ck_bytes["recompute"] = 0
     best = min(totals, key=totals.get)
+    # the backward kernel of the best configuration against HBM: what it must
+    # read (checkpoint slots, or the seed; hits; status; dL/dchi2) and write
+    # (dL/dm per layer, dL/dp0) once
+    every = int(best[len("checkpoint_every"):]) if best.startswith("checkpoint_every") else 0
+    n_slots = -(-L // every) if every else 0
+    bwd_bytes = (n * (n_slots * 27 * 4 + (0 if every else 27 * 4) + 4 + 4 + 6 * 4)
+                 + updates * (LAYER_BYTES + 3 * 4))
+    bwd_ms = ms[f"backward_checkpoint_every{every}" if every else "backward_recompute"]
+    bwd_gbs = bwd_bytes / (bwd_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(bwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(bwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "kf_adjoint_z_kernel", "hbm_algorithmic_bytes_per_launch": int(bwd_bytes),
+                "valu_frac_charged": None,
+                "note": "the backward's flops have no algorithmic count; HBM fraction only"}
     return {
         "metric": METRIC + " -- forward + adjoint of sum chi2",
         "value": round(updates / (totals[best] / 1e3), 1),
@@ -307,6 +321,7 @@ def bench_adjoint(args, sample):
         "config": {"workload": args.workload, "form": "adjoint", "tracks": n, "updates_per_step": updates,
                    "layout": args.layout, "best": best, "ms": {k: round(v, 4) for k, v in ms.items()},
                    "fwd_bwd_ms": {k: round(v, 4) for k, v in totals.items()}, "checkpoint_bytes": ck_bytes},
+        "roofline": roofline,
     }
 
 
