@@ -556,8 +556,8 @@ def main(argv=None):
                     help="only copy a 1 GiB device buffer --steps times (calibrates the HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU: the step has no cross-GPU work and this build runs on a "
-              "single MI355X; run it with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: tracks are independent and the step has no cross-GPU "
+              "work; run it with --gpus 1", file=sys.stderr)
         return 2
 
     import torch

@@ -77,7 +77,7 @@ typedef enum {
   KF_E_LAUNCH = 6,    /* the HIP runtime refused the launch */
   KF_E_WORKSPACE = 7, /* workspace missing or too small */
   KF_E_FLAGS = 8,     /* unknown flag bits or tuning values */
-  KF_E_UNSUPPORTED = 9 /* valid request this build does not implement */
+  KF_E_UNSUPPORTED = 9 /* valid request the library does not implement */
 } kf_status_t;
 
 enum { KF_SOA = 0, KF_AOSOA = 1, KF_AOS = 2 };

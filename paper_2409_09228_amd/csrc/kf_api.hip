@@ -568,7 +568,7 @@ const char* kf_status_string(kf_status_t s) {
     case KF_E_LAUNCH: return "kernel launch failed";
     case KF_E_WORKSPACE: return "workspace missing or too small";
     case KF_E_FLAGS: return "unknown flags or tuning values";
-    case KF_E_UNSUPPORTED: return "not supported by this build";
+    case KF_E_UNSUPPORTED: return "not supported by the library";
   }
   return "unknown status";
 }
