@@ -541,7 +541,7 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
-                    help="batched form: search the launch shape first and time the winner")
+                    help="batched and plain forms: search the launch shape and layout first, then time the winner")
     ap.add_argument("--form", default="auto", choices=["auto", "plain", "batched", "adjoint", "host", "f64", "smooth", "gate"],
                     help="auto: batched for mixed-geometry workloads, plain otherwise; host: host-resident "
                          "arrays, transfers included; f64: the full-FP64 form; smooth: filter + RTS smoother; gate: hit selection")
@@ -600,6 +600,16 @@ def main(argv=None):
         return 0
     if mixed:
         raise SystemExit("the plain form needs a single-geometry workload")
+    tuned = None
+    if args.autotune:
+        # block size and layout timed on this sample before the benchmark
+        from paper_2409_09228_amd import tune as T
+        t0 = time.perf_counter()
+        res = T.tune_plain(sample, flags=args.flags, use_cache=False)
+        c = res["config"]
+        args.block, args.layout = c["block"], c["layout"]
+        tuned = {"config": c, "search_s": round(time.perf_counter() - t0, 1), "candidates": len(res["tried"]),
+                 "worst_ms": round(max(t for _, t in res["tried"]), 4)}
     layout = parse_layout(args.layout)
     geom = int(sample["geom"][0])
     st = K.stage_sample(sample, layout)
@@ -716,7 +726,8 @@ def main(argv=None):
                                             "max": round(per[-1], 4),
                                             "note": "diagnostic: each launch between its own pair of events, "
                                                     "which adds a gap per launch; the timed figure is "
-                                                    "launch_ms_mean (back-to-back launches)"}},
+                                                    "launch_ms_mean (back-to-back launches)"},
+                   "autotune": tuned},
         "roofline": roof,
     }
     if not args.no_cpu:
