@@ -45,8 +45,8 @@ struct LaidOutHits {
     ln.template ld_all<3>(ln.hp, a.hit_pos, k, m);
     ln.template ld_all<6>(ln.hc, a.hit_cov, k, V);
   }
-  // AoS records (and FP64 arrays) are fetched into registers; element-major
-  // float layouts through LDS
+  // element-major float layouts can go through the LDS ring; AoS records
+  // (and FP64 arrays) are fetched into registers
   static constexpr bool kStaged = KIND != KF_AOS && sizeof(T) == 4;
   __device__ __forceinline__ int next(int k) const { return k + 1 < a.L ? k + 1 : k; }
   __device__ __forceinline__ int n_layers() const { return a.L; }
@@ -83,7 +83,18 @@ struct LaidOutCkpt {
 #define KF_STEP_OCCUPANCY
 #endif
 
-// dynamic LDS: kRingFloats per wave of the block (layouts whose hits are staged).
+// How a step kernel fetches its hits.  Planes: the layer step is short, so
+// element-major layouts bring the hits through the per-wave LDS ring with
+// three layers in flight.  Cylinders: five Newton iterations make the step
+// long enough for one layer of register prefetch to cover the latency, and
+// each lane then loads only its own hit, without the ring's per-layer copies
+// and LDS reads (5 % faster on the barrel sample in SoA and AoSoA).
+template <int GEOM, int KIND, bool WIDE>
+constexpr bool ring_staged() {
+  return LaidOutHits<KIND, WIDE>::kStaged && GEOM == 0;
+}
+
+// dynamic LDS: kRingFloats per wave of the block (kernels that stage through the ring).
 // STREAM: every track runs all a.L layers, so each staged hit is read once
 // (no wave re-reads the last layers of finished tracks) and the copies carry
 // the non-temporal hint.
@@ -99,7 +110,7 @@ __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const St
   float chi2;
   uint32_t status;
   const LaidOutHits<KIND, WIDE> hits(a, ln, nl);
-  if constexpr (LaidOutHits<KIND, WIDE>::kStaged) {
+  if constexpr (ring_staged<GEOM, KIND, WIDE>()) {
     LayerRing<LaidOutHits<KIND, WIDE>, STREAM ? kStreamPolicy : 0> stager(hits, ring);
     run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
                           a.layer, a.b, chi2, status);
@@ -115,7 +126,7 @@ __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const St
 template <int GEOM, int PREC, int KIND, bool WIDE>
 static hipError_t launch_one(int block, const StepArgs& a, hipStream_t s) {
   const int64_t grid = (a.n + block - 1) / block;
-  constexpr bool kStaged = LaidOutHits<KIND, WIDE>::kStaged;
+  constexpr bool kStaged = ring_staged<GEOM, KIND, WIDE>();
   const size_t lds = kStaged ? size_t(block / 64) * kRingFloats * sizeof(float) : 0;
   // copies straight into LDS address it through the low 16 bits of M0
   static_assert(4 * kRingFloats * sizeof(float) <= 65536, "a 256-thread block's rings must lie in 64 KiB of LDS");
