@@ -177,7 +177,9 @@ kf_status_t kf_propagate_update_z(
  * cylinder at all (KF_S_NO_CROSSING otherwise).  A crossing whose radius still
  * misses r_l by more than 1e-4 * r_l after the five steps sets
  * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z (the checkpoints
- * feed kf_smooth).
+ * feed kf_smooth); the longer barrel step prefetches each lane's hits into
+ * registers in every layout, so the non-temporal form of the planes does not
+ * apply here.
  */
 kf_status_t kf_propagate_update_r(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,
