@@ -257,12 +257,12 @@ def _ragged_with_failures(name, n, seed):
 @pytest.mark.parametrize("layout", ["soa", "aosoa32", "aosoa128"])
 @pytest.mark.parametrize("block", [64, 128, 256])
 def test_staged_ragged_form_matches_register_form_bitwise(kf, name, layout, block):
-    """Per-track layer counts: element-major layouts stage the hits through
-    each wave's LDS ring (finished lanes re-read their last layer), AoS
-    records fetch them one layer ahead into registers.  Each track's
-    arithmetic is the same in both, so the results are identical, including
-    non-finite inputs, a track that fails part-way (recomputed up to its
-    failing layer) and the block tail."""
+    """Per-track layer counts: on planes, element-major layouts stage the
+    hits through each wave's LDS ring (finished lanes re-read their last
+    layer); AoS records, and cylinders in every layout, fetch them one layer
+    ahead into registers.  Each track's arithmetic is the same in all, so the
+    results are identical, including non-finite inputs, a track that fails
+    part-way (recomputed up to its failing layer) and the block tail."""
     n = 5000 + block // 2 + 3
     s, j = _ragged_with_failures(name, n, 11)
     tune = (block, 1)
