@@ -46,3 +46,29 @@ def test_tuning_run_on_gpu(tmp_path):
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+@pytest.mark.gpu
+def test_plain_tuning_run_on_gpu(tmp_path):
+    """tune_plain times block size x layout on the sample, caches the pick,
+    and the picked configuration gives the default's results bit for bit
+    (each track's arithmetic does not depend on the layout or block)."""
+    torch = pytest.importorskip("torch")
+    from paper_2409_09228_amd import kf as K
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    sub = S.subset(S.generate("p2r_100x9600", n_events=1), np.arange(5000))
+    space = {"block": (64, 256), "layout": ("soa", "aos", "aosoa64")}
+    path = str(tmp_path / "t.json")
+    res = T.tune_plain(sub, reps=3, space=space, cache_path=path)
+    assert len(res["tried"]) == 6 and res["ms"] > 0
+    c = res["config"]
+    assert T.tune_plain(sub, space=space, cache_path=path)["config"] == c  # cached
+    st0 = K.stage_sample(sub, K.SOA)
+    st1 = K.stage_sample(sub, T.LAYOUTS[c["layout"]])
+    a = K.run_staged(st0)
+    b = K.run_staged(st1, tune=(c["block"], 1))
+    torch.cuda.synchronize()
+    for x, y in zip(K.results_to_logical(st0, a[0], a[1]), K.results_to_logical(st1, b[0], b[1])):
+        np.testing.assert_array_equal(x, y)
+    assert torch.equal(a[2], b[2]) and torch.equal(a[3], b[3])
