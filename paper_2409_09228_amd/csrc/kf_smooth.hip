@@ -263,11 +263,24 @@ __global__ void __launch_bounds__(256) kf_smooth_kernel(const SmoothArgs a) {
   Frame f1{0.0f, 0.0f};
   ln.template ld_all<6>(ln.par, a.par, 0, p1);
   ln.template ld_all<21>(ln.cov, a.cov, 0, C);
+  // checkpoint slot k's parameters, fetched one iteration ahead of their use
+  // (planes do not need slot 0: zeros)
+  float nx[6] = {};
+  if (nd == a.L && (GEOM == 1 || a.L - 1 > 0)) ln.template ld_first<27, 6>(ln.ck, a.ckpt, a.L - 1, nx);
   for (int k = a.L - 1; k >= 0; --k) {
-    if (k >= nd) continue;
     // layer k - 1's filtered parameters (checkpoint slot k), or the seed
-    float pm[6] = {};
-    if (GEOM == 1 || k > 0) ln.template ld_first<27, 6>(ln.ck, a.ckpt, k, pm);
+    float pm[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) pm[e] = nx[e];
+    if (k - 1 >= 0 && k - 1 < nd) {
+      if (GEOM == 1 || k - 1 > 0) {
+        ln.template ld_first<27, 6>(ln.ck, a.ckpt, k - 1, nx);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) nx[e] = 0.0f;
+      }
+    }
+    if (k >= nd) continue;
     // cylinder: the prediction into layer k gives layer k's frame and the
     // Jacobian of the next step back (one propagation per layer and lane,
     // whichever branch below the lane takes)
