@@ -214,3 +214,31 @@ def test_autograd_function(kf):
         gh = hp.grad.cpu().numpy().transpose(2, 0, 1).astype(np.float64)
         assert _rel(gp, rp) <= tp
         assert _rel(gh, rh) <= th
+
+
+def test_64bit_addressing_matches_32bit(kf):
+    """640,000 tracks x 64 planes put the kernels in their 64-bit address
+    form; the first 20,000 tracks on their own take the 32-bit buffer form.
+    Same arithmetic: forward and backward agree bit for bit on those tracks
+    (checkpoints of every 2nd layer, so the backward also replays segments)."""
+    w = S.Workload("p2z_64x640k", "z", 64, 10000, 64, seed_index=9)
+    s = S.generate(w)
+    m = 20000
+
+    def run(sample):
+        st = kf.stage_sample(sample, kf.SOA)
+        n, L = st["n"], st["L"]
+        ck = kf.checkpoint_buffer(n, L, kf.SOA, every=2)
+        po, co, c2, ss = kf.propagate_update_z(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                                               st["bz"], n, nlay=st["nlay"], layout=kf.SOA, ckpt=ck, ckpt_every=2)
+        wt = torch.ones(n, device="cuda")
+        gh, gp, gc = kf.chi2_backward_z(st, ss, wt, ckpt=ck, want_cov=True, ckpt_every=2)
+        torch.cuda.synchronize()
+        return (gh.reshape(L, 3, n)[:, :, :m].cpu(), gp.reshape(6, n)[:, :m].cpu(), gc.reshape(21, n)[:, :m].cpu(),
+                c2[:m].cpu(), ss[:m].cpu())
+
+    assert s["par"].shape[0] * 64 * 27 * 4 >= 1 << 32
+    big = run(s)
+    small = run(S.subset(s, np.arange(m)))
+    for x, y in zip(big, small):
+        assert torch.equal(x, y)

@@ -172,3 +172,28 @@ def test_full_size_sampled(kf, name, geom):
     m = metrics(_stack(sp, sP, done), _stack(gp[:, idx], gP[:, idx], done), geom)
     print(name, m)
     assert_within(m, TOL_SMOOTH_FIT, name)
+
+
+@pytest.mark.parametrize("geom", ["z", "r"])
+def test_64bit_addressing_matches_32bit(kf, geom):
+    """640,000 tracks x 64 layers put the filter and the smoother in their
+    64-bit address form; the first 20,000 tracks on their own take the 32-bit
+    buffer form.  Same arithmetic: the smoothed states agree bit for bit."""
+    w = S.Workload(f"p2{geom}_64x640k", geom, 64, 10000, 64, seed_index=9)
+    s = S.generate(w)
+    m = 20000
+    assert s["par"].shape[0] * 64 * 27 * 4 >= 1 << 32
+
+    def run(sample):
+        st = kf.stage_sample(sample, kf.SOA)
+        po, co, c2, ss, sm = kf.fit_smooth(st, in_place=True)
+        torch.cuda.synchronize()
+        L, n = st["L"], st["n"]
+        return sm.reshape(L, 27, n)[:, :, :m], ss[:m]
+
+    big, sb = run(s)
+    small, ss = run(S.subset(s, np.arange(m)))
+    assert torch.equal(sb, ss)
+    written = torch.arange(64, device="cuda")[:, None] < (ss >> 16)[None, :]
+    for e in range(27):
+        assert torch.equal(big[:, e][written], small[:, e][written])
