@@ -189,3 +189,22 @@ def test_streamed_and_counted_forms_agree_bitwise(kf):
     for x, y in ((a.par_out, b.par_out), (a.cov_out, b.cov_out), (a.chi2, b.chi2), (a.status, b.status),
                  (a.chosen, b.chosen)):
         assert torch.equal(x, y)
+
+
+def test_64bit_addressing_matches_32bit(kf):
+    """640,000 tracks x 64 planes (2 candidates per layer) put the kernel in
+    its 64-bit address form; the first 20,000 tracks on their own take the
+    32-bit buffer form.  Same arithmetic, same decisions: states, chi2,
+    status and the chosen candidates agree bit for bit."""
+    w = S.Workload("p2z_64x640k", "z", 64, 10000, 64, seed_index=9)
+    s = S.generate(w)
+    assert s["par"].shape[0] * 64 * 27 * 4 >= 1 << 32
+    mh = S.multi_hit(s, 2, spread=10.0, seed=3)
+    m = 20000
+    big = _gpu(kf, s, mh)
+    sub = S.subset(s, np.arange(m))
+    mhs = {k: (v[:, :m] if isinstance(v, np.ndarray) else v) for k, v in mh.items()}
+    small = _gpu(kf, sub, mhs)
+    for x, y in zip(big[:4], small[:4]):
+        np.testing.assert_array_equal(x[:m], y)
+    np.testing.assert_array_equal(big[4][:, :m], small[4])
