@@ -242,3 +242,22 @@ def test_64bit_addressing_matches_32bit(kf):
     small = run(S.subset(s, np.arange(m)))
     for x, y in zip(big, small):
         assert torch.equal(x, y)
+
+
+def test_full_size_sampled(kf):
+    """The full 614,400-track sample in the benchmark's best configuration
+    (checkpoints of every 2nd layer): gradients of 300 sampled tracks, the
+    last one included, against the FP64 dual-number reference."""
+    s = S.generate("p2z_64x9600")
+    n = s["par"].shape[0]
+    assert n == 614400
+    gh, gp, _, st, _ = _fwd_bwd(kf, s, checkpoint=True, every=2)
+    rng = np.random.default_rng(17)
+    idx = np.sort(rng.choice(n, 300, replace=False))
+    idx[-1] = n - 1
+    sub = S.subset(s, idx)
+    rh, rp, th, tp = _gates(sub)
+    eh, ep = _rel(gh[idx], rh), _rel(gp[idx], rp)
+    print("hit", eh, th, "par", ep, tp)
+    assert eh <= th and ep <= tp
+    assert np.all((st & 0xFF) == 0)
