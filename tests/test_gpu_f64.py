@@ -135,3 +135,20 @@ def test_p2r_no_crossing_f64(kf):
     ref = O.run_sample(s)
     np.testing.assert_array_equal(got[3], ref[3])
     assert np.all((ref[3] & 0xFF) == O.ST_NO_CROSSING)
+
+
+@pytest.mark.parametrize("name,geom", [("p2z_100x9600", 0), ("p2r_100x9600", 1)])
+def test_full_size_sampled_f64(kf, name, geom):
+    """The full 960,000-track samples in the benchmark's launch shape; 300
+    sampled tracks, the last one included, against the FP64 oracle."""
+    s = S.generate(name)
+    n = s["par"].shape[0]
+    got = _run(kf, s)
+    rng = np.random.default_rng(29)
+    idx = np.sort(rng.choice(n, 300, replace=False))
+    idx[-1] = n - 1
+    ref = O.run_sample(S.subset(s, idx))
+    m = metrics(ref, tuple(x[idx] for x in got), geom)
+    print(name, m)
+    assert_within(m, F64_TOL, f"{name} f64 full size")
+    np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
