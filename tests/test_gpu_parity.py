@@ -312,3 +312,21 @@ def test_64bit_addressing_matches_32bit(kf, geom, layout):
     ok = ((ref[3] & 0xFF) == 0) & np.all(np.isfinite(ref[0]), 1)
     f32 = metrics(ref, O.run_sample(sub, precision="f32"), g, mask=ok)
     assert_within(metrics(ref, tuple(x[idx] for x in got), g, mask=ok), calibrated(TOL_F32, f32), "64-bit form")
+
+
+@pytest.mark.parametrize("name,geom", [("p2z_100x9600", 0), ("p2r_100x9600", 1)])
+def test_precision_form_full_size_sampled(kf, name, geom):
+    """The precision form (FP64 inverse and Joseph update) on the full
+    960,000-track samples; 1000 sampled tracks, the last one included,
+    against the oracle's Joseph form."""
+    s = S.generate(name)
+    n = s["par"].shape[0]
+    got = _gpu_run(kf, s, flags=3)
+    rng = np.random.default_rng(31)
+    idx = np.sort(rng.choice(n, 1000, replace=False))
+    idx[-1] = n - 1
+    ref = _oracle(S.subset(s, idx), joseph=True)
+    m = metrics(ref, tuple(x[idx] for x in got), geom)
+    print(name, m)
+    assert_within(m, TOL_PRECISION, f"{name} flags=3 full size")
+    np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
