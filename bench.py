@@ -24,6 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "track-layer updates/sec (propagate+Kalman) FP32 at 1 GPU; % of HBM/VALU roofline"
 HBM_PEAK_GBS = 8000.0
+# kf_propagate_update_batched's launch shape when none is given (block,
+# tracks per thread, schedule, grid multiple), as include/kf.h states it
+BATCHED_DEFAULT_SHAPE = (128, 1, 1, 2)
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
@@ -187,8 +190,13 @@ def bench_batched(args, sample):
     par_out, cov_out = torch.empty_like(st["par"]), torch.empty_like(st["cov"])
     chi2 = torch.empty(n, device="cuda")
     status = torch.empty(n, dtype=torch.int32, device="cuda")
-    launch = K.BatchedLauncher(st, (par_out, cov_out), chi2, status, flags=args.flags,
-                               tune=(args.block, args.tpt, args.sched, args.waves_mult), stream=stream)
+    # no launch shape given: the library's default (tune = NULL)
+    shape = None
+    if any(v is not None for v in (args.block, args.tpt, args.sched, args.waves_mult)):
+        shape = (args.block or BATCHED_DEFAULT_SHAPE[0], args.tpt or BATCHED_DEFAULT_SHAPE[1],
+                 BATCHED_DEFAULT_SHAPE[2] if args.sched is None else args.sched,
+                 args.waves_mult or BATCHED_DEFAULT_SHAPE[3])
+    launch = K.BatchedLauncher(st, (par_out, cov_out), chi2, status, flags=args.flags, tune=shape, stream=stream)
     ms = time_launches(launch, args.steps, stream)
     ok = int(((status & 0xFF) == 0).sum().item())
     # baseline: one launch of the plain kernel per (geometry, layer count) bucket
@@ -244,8 +252,10 @@ def bench_batched(args, sample):
         "dtype": "f32" if args.flags == 0 else "f32+f64", "data": "synthetic",
         "config": {"workload": args.workload, "form": "persistent batched launch, hipGraph replay",
                    "tracks": n, "updates_per_step": updates, "state_layout": layout_name,
-                   "block": args.block, "tracks_per_thread": args.tpt, "schedule": args.sched,
-                   "waves_mult": args.waves_mult, "ok_tracks": ok,
+                   "launch_shape": "library default" if shape is None else "given",
+                   "block": (shape or BATCHED_DEFAULT_SHAPE)[0], "tracks_per_thread": (shape or BATCHED_DEFAULT_SHAPE)[1],
+                   "schedule": (shape or BATCHED_DEFAULT_SHAPE)[2], "waves_mult": (shape or BATCHED_DEFAULT_SHAPE)[3],
+                   "ok_tracks": ok,
                    "per_bucket_launches": len(launches), "per_bucket_ms": round(ms_b, 4),
                    "per_bucket_updates_per_s": round(updates / (ms_b / 1e3), 1),
                    "speedup_vs_per_bucket": round(ms_b / ms, 3), "autotune": tuned},
@@ -384,7 +394,7 @@ def bench_f64(args, sample):
     updates = int(sample["nlay"].sum())
     st = K.stage_sample_f64(sample, layout)
     stream = torch.cuda.current_stream()
-    launch = K.StepLauncherF64(st, flags=args.flags & 2, tune=(args.block, 1), stream=stream)
+    launch = K.StepLauncherF64(st, flags=args.flags & 2, tune=(args.block or 256, 1), stream=stream)
     for _ in range(args.warmup):
         launch()
     ms_step = time_launches(launch, args.steps, stream)
@@ -418,7 +428,7 @@ def bench_f64(args, sample):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "form": "full FP64", "tracks": n, "updates_per_step": updates,
-                   "layout": args.layout, "joseph": bool(args.flags & 2), "block": args.block, "ok_tracks": ok},
+                   "layout": args.layout, "joseph": bool(args.flags & 2), "block": args.block or 256, "ok_tracks": ok},
         "roofline": roof,
     }
 
@@ -442,9 +452,9 @@ def bench_smooth(args, sample):
     ss = torch.empty(n, dtype=torch.int32, device="cuda")
     fwd = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
                          out=(po, co), chi2=c2, status=ss, nlay=st["nlay"], layout=layout, ckpt=ck, ckpt_every=1,
-                         tune=(args.block, 1), stream=stream)
+                         tune=(args.block or 256, 1), stream=stream)
     out = K.checkpoint_buffer(n, L, layout, "cuda")
-    sm = K.SmoothLauncher(st, ck, po, co, ss, out=out, tune=(args.block, 1), stream=stream)
+    sm = K.SmoothLauncher(st, ck, po, co, ss, out=out, tune=(args.block or 256, 1), stream=stream)
     fwd()
     for _ in range(args.warmup):
         sm()
@@ -494,7 +504,7 @@ def bench_gate(args, sample):
     cands = K.stage_candidates(st, mh)
     del mh
     stream = torch.cuda.current_stream()
-    run = K.GateLauncher(st, cands, args.gate, tune=(args.block, 1), stream=stream)
+    run = K.GateLauncher(st, cands, args.gate, tune=(args.block or 256, 1), stream=stream)
     for _ in range(args.warmup):
         run()
     ms = time_launches(run, args.steps, stream)
@@ -534,10 +544,11 @@ def main(argv=None):
     ap.add_argument("--workload", default="p2z_100x9600")
     ap.add_argument("--layout", default="soa")
     ap.add_argument("--flags", type=int, default=0)
-    ap.add_argument("--block", type=int, default=256)
-    ap.add_argument("--tpt", type=int, default=1)
-    ap.add_argument("--sched", type=int, default=0, help="batched form: 0 dynamic queue, 1 static round-robin")
-    ap.add_argument("--waves-mult", type=int, default=1, help="batched form: grid in units of resident blocks")
+    ap.add_argument("--block", type=int, default=None,
+                    help="threads per block (default 256; the batched form: the library's default shape)")
+    ap.add_argument("--tpt", type=int, default=None, help="tracks per thread (default 1)")
+    ap.add_argument("--sched", type=int, default=None, help="batched form: 0 dynamic queue, 1 static round-robin")
+    ap.add_argument("--waves-mult", type=int, default=None, help="batched form: grid in units of resident blocks")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
@@ -619,6 +630,7 @@ def main(argv=None):
     cov_out = torch.empty_like(st["cov"])
     chi2 = torch.empty(n, dtype=torch.float32, device="cuda")
     status = torch.empty(n, dtype=torch.int32, device="cuda")
+    args.block, args.tpt = args.block or 256, args.tpt or 1
     tune = (args.block, args.tpt)
     stream = torch.cuda.current_stream()
 

@@ -86,7 +86,8 @@ typedef struct {
   int32_t block; /* AoSoA block width B; ignored for KF_SOA */
 } kf_layout_t;
 
-/* Launch shape; pass NULL for the built-in default (256, 1, dynamic, 1).
+/* Launch shape; pass NULL for the built-in default: (256, 1, dynamic, 1), and
+ * (128, 1, static, 2) for kf_propagate_update_batched.
  *   block_threads      64, 128 or 256
  *   tracks_per_thread  1 or 2; the plain kernels use 1 whatever is asked;
  *                      the batched kernel gives each lane this many tracks of a

@@ -454,7 +454,9 @@ kf_status_t kf_propagate_update_batched(
   kf::TrackLayout tl;
   if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
   if (flags & ~uint32_t(KF_F_PRECISION | KF_F_NO_GRAPH)) return KF_E_FLAGS;
-  int block = 256, tpt = 1, sched = KF_SCHED_DYNAMIC, mult = 1;
+  // default shape: the one measured fastest on a mixed uneven batch (static
+  // round-robin over a grid of twice the resident 128-thread blocks)
+  int block = 128, tpt = 1, sched = KF_SCHED_STATIC, mult = 2;
   if (tune) {
     block = tune->block_threads;
     tpt = tune->tracks_per_thread;

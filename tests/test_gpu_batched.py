@@ -102,7 +102,8 @@ def test_graph_replays_match_eager(kf, uneven):
     kf.release_graphs()
 
 
-@pytest.mark.parametrize("tune", [(64, 1, 0, 1), (128, 2, 0, 1), (256, 2, 1, 1), (64, 1, 0, 2), (256, 1, 1, 4)])
+@pytest.mark.parametrize("tune", [(64, 1, 0, 1), (128, 2, 0, 1), (256, 2, 1, 1), (64, 1, 0, 2), (256, 1, 1, 4),
+                                  (256, 1, 0, 1), (128, 1, 1, 2)])
 def test_launch_shapes_give_identical_results(kf, uneven, tune):
     sub = S.subset(uneven, np.arange(10000))
     st = kf.stage_batched(sub, kf.AOS)
