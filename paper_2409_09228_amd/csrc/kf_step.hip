@@ -98,11 +98,62 @@ constexpr bool ring_staged() {
 // STREAM: every track runs all a.L layers, so each staged hit is read once
 // (no wave re-reads the last layers of finished tracks) and the copies carry
 // the non-temporal hint.
+// Cylinders with per-track layer counts: a wave runs as many layers as its
+// longest track, and tracks stop where the helix no longer reaches a cylinder
+// (on the barrel sample 36 % of the lanes idle).  Each group of KF_CYL_SORT
+// consecutive tracks is therefore handed to its threads longest first, so
+// that a wave's tracks have similar lengths (1.27x fewer lane-layers for
+// groups of 128).  With register prefetch every lane loads its own hits, so
+// the permutation costs only a wider spread of each load: a 128-track group
+// spans 4 cache lines per element row instead of 2 (SoA; AoS records are
+// contiguous), while 256-track groups cost more than they save.  0 disables.
+#ifndef KF_CYL_SORT
+#define KF_CYL_SORT 128
+#endif
+// The track this thread runs, longest first within each group of G threads
+// of the block (a counting sort of the layer counts in LDS; G <= 256).
+template <int G>
+__device__ __forceinline__ int64_t by_length(const StepArgs& a) {
+  __shared__ int cnt[256 / G][KF_MAX_LAYERS + 2];
+  __shared__ int off[256 / G][KF_MAX_LAYERS + 2];
+  __shared__ int perm[256];
+  const int t = int(threadIdx.x), nt = int(blockDim.x);
+  const int gs = nt < G ? nt : G;  // group size
+  const int g = t / gs, lt = t - g * gs;
+  const int ng = nt / gs;
+  const int64_t i0 = int64_t(blockIdx.x) * nt;
+  int key = a.L + 1;  // no track: last
+  if (i0 + t < a.n) {
+    int nl = a.nlay[i0 + t];
+    nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
+    key = a.L - nl;
+  }
+  for (int j = t; j < ng * (KF_MAX_LAYERS + 2); j += nt) cnt[j / (KF_MAX_LAYERS + 2)][j % (KF_MAX_LAYERS + 2)] = 0;
+  __syncthreads();
+  const int r = atomicAdd(&cnt[g][key], 1);
+  __syncthreads();
+  // exclusive prefix of each group's counts (a serial sum per entry: at most
+  // KF_MAX_LAYERS + 1 terms)
+  for (int j = t; j < ng * (KF_MAX_LAYERS + 2); j += nt) {
+    const int gg = j / (KF_MAX_LAYERS + 2), kk = j % (KF_MAX_LAYERS + 2);
+    int excl = 0;
+    for (int k = 0; k < kk; ++k) excl += cnt[gg][k];
+    off[gg][kk] = excl;
+  }
+  __syncthreads();
+  perm[g * gs + off[g][key] + r] = lt;
+  __syncthreads();
+  return i0 + g * gs + perm[t];
+}
+
 template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM>
 __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const StepArgs a) {
   extern __shared__ float kf_lds[];
   float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kRingFloats;
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if constexpr (GEOM == 1 && KF_CYL_SORT > 0) {
+    if (a.nlay) i = by_length<KF_CYL_SORT>(a);
+  }
   if (i >= a.n) return;
   const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.Lck);
   int nl = a.nlay ? a.nlay[i] : a.L;
