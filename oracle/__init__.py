@@ -24,24 +24,46 @@ ST_NO_CROSSING = 4
 ST_NEWTON_RESIDUAL = 8
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with g++ (no fast-math: IEEE results)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", _LIB + ".tmp", _SRC]
+# g++ flags: IEEE arithmetic (no fast-math; -std=c++17 keeps multiply-adds
+# unfused), OpenMP over tracks.  The in-tree build targets the generic x86-64
+# ISA so that it runs on any host it is copied to.
+CXXFLAGS = ["-O3", "-std=c++17", "-fopenmp", "-fPIC", "-shared"]
+
+
+def build(force: bool = True, out: str | None = None, native: bool = False) -> str:
+    """Compile the oracle with g++.  native=True adds -march=native (the host
+    the library is built on must be the one that runs it)."""
+    path = _LIB if out is None else out
+    if force or not os.path.exists(path):
+        cmd = ["g++", *CXXFLAGS, *(["-march=native"] if native else []), "-o", path + ".tmp", _SRC]
         subprocess.run(cmd, check=True)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(path + ".tmp", path)
+    return path
 
 
 _lib = None
+_lib_path = None
+
+
+def use_native_build(directory: str) -> str:
+    """Build the oracle with -march=native for this host into `directory` and
+    load that copy instead of the in-tree one (the CPU-baseline timing).
+    Returns the library's path."""
+    global _lib, _lib_path
+    path = build(force=True, out=os.path.join(directory, "libkforacle_native.so"), native=True)
+    _lib = None
+    _lib_path = path
+    lib()
+    return path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _lib_path or _LIB
+        if not os.path.exists(path):
             build()
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         d, f, i32, u32 = (ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint32))
         c_int, c_i64, c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_double
@@ -49,6 +71,7 @@ def lib():
         L.kfo_run_f32.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, f, f, f, f, c_int, f, f, f, i32, c_int]
         L.kfo_propagate.argtypes = [c_int, d, c_dbl, c_dbl, d, d, u32]
         L.kfo_update.argtypes = [d, d, d, d, c_int, d, d, d, u32]
+        L.kfo_newton_r.argtypes = [d, c_dbl, c_dbl, d, d]
         L.kfo_grad_chi2.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, c_int]
         L.kfo_grad_chi2_f32.argtypes = L.kfo_grad_chi2.argtypes
         L.kfo_filter_record.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, d, d, d,
@@ -122,6 +145,18 @@ def propagate(geom: int, p, target: float, bz: float):
     lib().kfo_propagate(int(geom), _p(p, ctypes.c_double), float(target), float(bz),
                         _p(po, ctypes.c_double), _p(F, ctypes.c_double), ctypes.byref(fl))
     return po, F, fl.value
+
+
+def newton_r(p, rk: float, bz: float):
+    """The method's five-step crossing search for cylinder rk on its own
+    (single precision): (fifth iterate s, |x(s)^2 + y(s)^2 - rk^2| / rk^2).
+    The oracle's crossing is the closed form; this search decides the
+    ST_NEWTON_RESIDUAL flag."""
+    p = np.ascontiguousarray(p, np.float64)
+    s = ctypes.c_double(0.0)
+    rel = ctypes.c_double(0.0)
+    lib().kfo_newton_r(_p(p, ctypes.c_double), float(rk), float(bz), ctypes.byref(s), ctypes.byref(rel))
+    return s.value, rel.value
 
 
 def update(p, P21, m, V6, joseph=False):

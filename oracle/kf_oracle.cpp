@@ -32,11 +32,13 @@
 //   element (i, j), i >= j, sits at i*(i+1)/2 + j (21 entries for 6x6,
 //   6 for 3x3: xx, yx, yy, zx, zy, zz).
 //   Per-track status: bit 0 non-finite value, bit 1 residual covariance not
-//   positive definite, bit 2 cylinder not reachable, bit 3 reserved for the
-//   iterative propagation's residual check (never set here); bits 16..31 hold
-//   the number of layers applied.  A track stops at its first failing layer
+//   positive definite, bit 2 surface not reachable (a cylinder beyond the
+//   helix's reach, or a plane parallel to the track's direction), bit 3 the
+//   method's fixed five-step crossing search ends off the cylinder (see
+//   newton_crossing_f32); bits 16..31 hold the number of layers applied.  A track stops at its first failing layer
 //   and keeps the state from before that layer.  Within a layer the checks
-//   run in this order: surface reachable; hit, propagated state and Jacobian
+//   run in this order: surface reachable; the crossing search lands on the
+//   cylinder; hit, propagated state and Jacobian
 //   finite; residual covariance positive definite; updated state finite.
 //   Process noise is zero (no material effects).
 
@@ -58,7 +60,7 @@ using std::atan2; using std::asin; using std::fabs; using std::isfinite;
 constexpr double kCLight = 0.00299792458;
 constexpr double kPi = 3.14159265358979323846;
 
-enum : uint32_t { ST_NONFINITE = 1u, ST_NOT_PD = 2u, ST_NO_CROSSING = 4u };
+enum : uint32_t { ST_NONFINITE = 1u, ST_NOT_PD = 2u, ST_NO_CROSSING = 4u, ST_NEWTON_RESIDUAL = 8u };
 
 // ---------------------------------------------------------------- dual numbers
 // a + sum_i d_i eps_i with eps_i eps_j = 0: exact first derivatives.
@@ -198,12 +200,58 @@ template <class S> V6<S> helix_at(const V6<S>& p, const S& s, double b) {
 }
 
 // Propagate to the endcap plane z = zk (the "propagation to z" benchmark):
-// the helix reaches it after s = (zk - z0) * tan(theta).
+// the helix reaches it after s = (zk - z0) * tan(theta).  A track whose
+// direction is parallel to the planes never reaches one; the reading taken
+// here is that a plane is out of reach when |cos theta| < 1e-6 (within 1e-6
+// rad of theta = pi/2, where reaching a plane 1 cm away takes 10 km of
+// transverse path).
+constexpr double kPlaneCosMin = 1e-6;
 template <class S> V6<S> to_plane(const V6<S>& p, double zk, double b, uint32_t& flags) {
-  (void)flags;
+  if (!(fabs(std::cos(val(p[ITH]))) >= kPlaneCosMin)) { flags |= ST_NO_CROSSING; return p; }
   S s = (zk - p[IZ]) * tan(p[ITH]);
   return helix_at(p, s, b);
 }
+
+// The method's own cylinder-crossing search (Sec. 3.2: the barrel
+// propagation is iterative, in a fixed number of steps): start from the
+// straight line's crossing s0 = -beta + sqrt(beta^2 - rho0^2 + rk^2), with
+// beta = x cos(phi) + y sin(phi) and rho0^2 = x^2 + y^2 (s0 = -beta when the
+// square root's argument is negative), then take five Newton steps on
+// g(s) = x(s)^2 + y(s)^2 - rk^2, g'(s) = 2 (x(s) cos phi(s) + y(s) sin phi(s)).
+// The oracle's crossing is the closed form below; this search only decides
+// status bit 3 (its fifth iterate is off the cylinder: |g| > 2e-4 rk^2, which
+// happens only next to a tangent crossing, where the root is nearly double
+// and Newton's method slows down).  It runs in single precision, the
+// precision of the FP32 path whose flag it mirrors.  Returns the fifth
+// iterate; *rel = |g| / rk^2 there.
+inline float newton_crossing_f32(double xd, double yd, double kappa, double phid, double rkd, double bd,
+                                 float* rel) {
+  const float x = float(xd), y = float(yd), phi = float(phid), rk = float(rkd);
+  const float om = -float(bd) * float(kappa);
+  const float c0 = std::cos(phi), s0 = std::sin(phi);
+  const float beta = x * c0 + y * s0;
+  const float rk2 = rk * rk;
+  float s = -beta + std::sqrt(std::max(beta * beta - (x * x + y * y) + rk2, 0.0f));
+  float X = x, Y = y, cph = c0, sph = s0;
+  auto point = [&](float t) {
+    const float u = 0.5f * om * t;
+    const float sincu = u == 0.0f ? 1.0f : std::sin(u) / u;
+    X = x + t * sincu * std::cos(phi + u);
+    Y = y + t * sincu * std::sin(phi + u);
+    cph = std::cos(phi + om * t);
+    sph = std::sin(phi + om * t);
+  };
+  for (int it = 0; it < 5; ++it) {
+    point(s);
+    const float g = X * X + Y * Y - rk2;
+    const float gp = 2.0f * (X * cph + Y * sph);
+    s = s - g / gp;
+  }
+  point(s);
+  *rel = std::fabs(X * X + Y * Y - rk2) / rk2;
+  return s;
+}
+constexpr float kNewtonResidualMax = 2e-4f;
 
 // Propagate to the barrel cylinder r = rk (the "propagation to r" benchmark):
 // the first crossing at s > 0.  The transverse circle has centre
@@ -241,6 +289,11 @@ template <class S> V6<S> to_cylinder(const V6<S>& p, double rk, double b, uint32
       if (!have || val(t) < val(s)) { s = t; have = true; }
     }
   }
+  // the crossing exists; flag it if the method's own search misses it (the
+  // state returned is still the exact crossing)
+  float rel;
+  newton_crossing_f32(val(p[IX]), val(p[IY]), val(p[IK]), val(p[IPHI]), rk, b, &rel);
+  if (!(rel <= kNewtonResidualMax)) flags |= ST_NEWTON_RESIDUAL;
   return helix_at(p, s, b);
 }
 
@@ -733,6 +786,17 @@ int kfo_propagate(int geom, const double* p, double target, double bz, double* p
     for (int j = 0; j < 6; ++j) F_out[i * 6 + j] = F[i][j];
   }
   *flags = f;
+  return 0;
+}
+
+// The method's five-step crossing search on its own (newton_crossing_f32):
+// p [6], cylinder radius rk; returns the fifth iterate s and |g(s)| / rk^2.
+int kfo_newton_r(const double* p, double rk, double bz, double* s_out, double* rel_out) {
+  float rel = 0.0f;
+  const float s = kfo::newton_crossing_f32(p[kfo::IX], p[kfo::IY], p[kfo::IK], p[kfo::IPHI], rk,
+                                           kfo::kCLight * bz, &rel);
+  *s_out = double(s);
+  *rel_out = double(rel);
   return 0;
 }
 
