@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "track-layer updates/sec (propagate+Kalman) FP32 at 1 GPU; % of HBM/VALU roofline"
+DEFAULT_WORKLOAD = "p2z_100x9600"
+P2R_WORKLOAD = "p2r_100x9600"
 HBM_PEAK_GBS = 8000.0
 # kf_propagate_update_batched's launch shape when none is given (block,
 # tracks per thread, schedule, grid multiple), as include/kf.h states it
@@ -98,7 +100,38 @@ def parse_layout(s: str):
     raise SystemExit(f"unknown layout {s}")
 
 
-def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0):
+def cpu_identity() -> dict:
+    """The host CPU as /proc/cpuinfo and lscpu name it (vendor, family,
+    model and stepping numbers as well: a virtualised host may shorten the
+    model string)."""
+    info = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                if info:
+                    break
+                continue
+            k, v = (x.strip() for x in line.split(":", 1))
+            if k in ("vendor_id", "cpu family", "model", "model name", "stepping") and k not in info:
+                info[k] = v
+            if k == "flags" and "flags" not in info:
+                fl = v.split()
+                info["flags"] = " ".join(f for f in ("avx2", "fma", "avx512f") if f in fl)
+    except OSError:
+        pass
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+                info["lscpu " + k.strip()] = v.strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0, build: str = ""):
     """The FP64 oracle on the first n_tracks of the same sample with all host
     cores, repeated until at least min_seconds of wall time (a bounded
     sample of the workload); then one thread on a twentieth of it for about
@@ -126,22 +159,231 @@ def cpu_baseline(sample, n_tracks: int, min_seconds: float = 10.0):
         O.run_sample(one, nthreads=1)
         r1 += 1
     d1 = time.perf_counter() - t1
-    model = ""
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    ident = cpu_identity()
     return {"value": upd / med, "unit": "track-layer updates/s", "cores": threads, "kind": "oracle",
-            "cpu_model": model,
+            "cpu_model": ident.get("lscpu Model name") or ident.get("model name", ""),
+            "cpu": ident, "build": build,
             "sample": f"first {len(idx)} tracks ({upd} track-layer updates) of the same sample, FP64, OpenMP "
                       f"over tracks; median of {reps} passes ({dt:.1f} s wall in all)",
             "mean_value": upd * reps / dt,
             "single_thread_value": u1 * r1 / d1,
             "single_thread_sample": f"first {one['par'].shape[0]} tracks ({u1} updates), 1 thread, "
                                     f"{r1} passes in {d1:.1f} s"}
+
+
+# floors of the floored relative parameter error: cm, cm, cm, 1/GeV, rad, rad
+PAR_FLOOR = np.array([1.0, 1.0, 1.0, 0.1, 1.0, 1.0])
+PAR_NAMES = ("x", "y", "z", "kappa", "phi", "theta")
+
+
+def _sym6(P21):
+    out = np.zeros(P21.shape[:-1] + (6, 6))
+    k = 0
+    for i in range(6):
+        for j in range(i + 1):
+            out[..., i, j] = out[..., j, i] = P21[..., k]
+            k += 1
+    return out
+
+
+def output_errors(ref, got, geom: int) -> dict:
+    """Per-output error of `got` against the FP64 reference `ref` (both
+    (par [n,6], cov [n,21], chi2 [n], status [n])): the floored relative
+    error of each parameter, |d p| / max(|p|, floor), floors (1 cm, 1 cm,
+    1 cm, 0.1 /GeV, 1 rad, 1 rad), phi compared modulo 2 pi; the largest
+    parameter error in units of its standard deviation; the covariance in
+    correlation units |d C_ij| / sqrt(C_ii C_jj) (on planes without the z row,
+    which is zero on both sides; on cylinders x and y normalised by the
+    transverse variance, since the radial direction has none); the relative
+    error of each diagonal element, unfloored; chi2 relative (floored at 1);
+    and the status words that differ."""
+    po, co, c2, st = ref
+    qo, qc, q2, qs = got
+    d = qo - po
+    d[:, 4] = np.angle(np.exp(1j * d[:, 4]))
+    P, Q = _sym6(co), _sym6(qc)
+    v = np.diagonal(P, axis1=-2, axis2=-1).copy()
+    if geom == 1:
+        v[:, 0] = v[:, 1] = v[:, 0] + v[:, 1]
+    keep = [0, 1, 3, 4, 5] if geom == 0 else list(range(6))
+    norm = np.sqrt(v[:, :, None] * v[:, None, :])
+    if geom == 0:
+        norm[:, 2, :] = np.inf
+        norm[:, :, 2] = np.inf
+    dg = np.abs(np.diagonal(Q - P, axis1=-2, axis2=-1))[:, keep] / np.diagonal(P, axis1=-2, axis2=-1)[:, keep]
+    fl = (np.abs(d) / np.maximum(np.abs(po), PAR_FLOOR)).max(0)
+    out = {name: float(f"{fl[i]:.3g}") for i, name in enumerate(PAR_NAMES)}
+    out["par_sigma"] = float(f"{(np.abs(d[:, keep]) / np.sqrt(v[:, keep])).max():.3g}")
+    out["cov_corr"] = float(f"{(np.abs(Q - P) / norm).max():.3g}")
+    out["cov_diag_rel_raw"] = float(f"{dg.max():.3g}")
+    out["chi2_rel"] = float(f"{(np.abs(q2 - c2) / np.maximum(c2, 1.0)).max():.3g}")
+    out["status_mismatch"] = int(np.sum(st != qs))
+    return out
+
+
+def precision_errors(sample, res, n_sample: int = 20000) -> dict:
+    """The GPU's results for precision flags 0 (FP32), 1 (FP64 inverse and
+    gain) and 3 (FP64 inverse, gain and Joseph update) on the full workload,
+    launched as timed, against the FP64 oracle on n_sample evenly spaced
+    tracks (the last one included).  The oracle takes the plain update for
+    flags 0 and 1, the Joseph form for flag 3."""
+    import torch
+    import oracle as O
+    from paper_2409_09228_amd import kf as K
+    from paper_2409_09228_amd import synth as S
+    n = sample["par"].shape[0]
+    idx = np.unique(np.linspace(0, n - 1, min(n_sample, n)).astype(np.int64))
+    sub = S.subset(sample, idx)
+    geom = int(sample["geom"][0])
+    st = res["staged"]
+    out = {"tracks_compared": int(len(idx)), "workload": res["config"]["workload"],
+           "reference": "FP64 oracle (plain update for flags 0 and 1, Joseph form for flag 3)"}
+    refs = {}
+    for flags in (0, 1, 3):
+        joseph = bool(flags & 2)
+        if joseph not in refs:
+            refs[joseph] = O.run_sample(sub, joseph=joseph)
+        po, co, c2, ss = res["outputs"]
+        launch = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"],
+                                st["n"], out=(po, co), chi2=c2, status=ss, nlay=st["nlay"], layout=st["layout"],
+                                flags=flags, tune=res["tune"], stream=torch.cuda.current_stream())
+        launch()
+        torch.cuda.synchronize()
+        p, c = K.results_to_logical(st, po, co)
+        got = (p[idx], c[idx], c2.cpu().numpy().astype(np.float64)[idx], ss.cpu().numpy()[idx])
+        out[f"flags_{flags}"] = output_errors(refs[joseph], got, geom)
+    return out
+
+
+def oracle_leg(sample, args, head, r_sample=None, r=None) -> dict:
+    """Everything bench.py does with the FP64 oracle, on the host: the CPU
+    baseline (the oracle built for this host with -O3 -march=native, timed on
+    a bounded part of the workload) and the per-output precision error of the
+    GPU's results on sampled tracks."""
+    import tempfile
+    import oracle as O
+    build = "g++ " + " ".join(O.CXXFLAGS) + " -march=native"
+    try:
+        tmp = tempfile.mkdtemp(prefix="kf_oracle_")
+        O.use_native_build(tmp)
+    except Exception as e:  # noqa: BLE001 -- the in-tree build still times the oracle
+        build = "g++ " + " ".join(O.CXXFLAGS) + f" (in-tree build; -march=native failed: {e})"
+    leg = {"cpu_baseline": cpu_baseline(sample, args.cpu_tracks, args.cpu_seconds, build)}
+    pe = {"p2z" if int(sample["geom"][0]) == 0 else "p2r": precision_errors(sample, head)}
+    if r is not None:
+        pe["p2r"] = precision_errors(r_sample, r)
+    leg["precision_error"] = pe
+    return leg
+
+
+def plain_roofline(geom: int, n: int, updates: int, ms_step: float, workload: str, layout: str, flags: int,
+                   streamed: bool) -> dict:
+    """Both fractions of the plain step over one launch: HBM (algorithmic
+    bytes) and VALU (algorithmic flops, transcendentals charged); the larger
+    one binds."""
+    flops = FLOPS_PER_UPDATE[geom] * updates
+    flops_c = FLOPS_CHARGED_PER_UPDATE[geom] * updates
+    bytes_ = TRACK_BYTES * n + LAYER_BYTES * updates
+    sec = ms_step / 1e3
+    hbm = bytes_ / sec / 1e9
+    tfl = flops / sec / 1e12
+    tfl_c = flops_c / sec / 1e12
+    fr_hbm = hbm / HBM_PEAK_GBS
+    fr_valu = tfl_c / FP32_PEAK_TFLOPS
+    if fr_hbm >= fr_valu:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(fr_hbm, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfl_c, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(fr_valu, 4), "traffic": None}
+    roof["intensity_flop_per_byte"] = round(flops / bytes_, 2)
+    roof["ridge_flop_per_byte"] = round(FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9), 2)
+    traffic = measured_traffic(workload, layout, flags)
+    if traffic is not None:
+        roof["traffic"] = traffic
+    roof["flops_per_update"] = FLOPS_PER_UPDATE[geom]
+    roof["flops_per_update_transcendentals_charged"] = FLOPS_CHARGED_PER_UPDATE[geom]
+    roof["valu_achieved_TFLOPs_charged"] = round(tfl_c, 3)
+    roof["valu_frac_charged"] = round(fr_valu, 4)
+    roof["valu_frac_charged_of_nonpacked_peak"] = round(tfl_c / FP32_PEAK_NONPACKED_TFLOPS, 4)
+    roof["alu_achieved_TFLOPs"] = round(tfl, 3)
+    roof["alu_frac"] = round(tfl / FP32_PEAK_TFLOPS, 4)
+    roof["frac_of_nonpacked_fp32_peak"] = round(tfl / FP32_PEAK_NONPACKED_TFLOPS, 4)
+    roof["hbm_algorithmic_bytes_per_launch"] = int(bytes_)
+    roof["hbm_achieved_GBs"] = round(hbm, 1)
+    roof["hbm_frac"] = round(fr_hbm, 4)
+    roof["kernel"] = "kf_step_kernel<%d,%d,%s,%s>" % (geom, {0: 0, 1: 1, 3: 2}.get(flags, 0), layout,
+                                                   "streamed" if streamed else "counted")
+    roof["kernel_source_sha256"] = kernel_source_digest()
+    return roof
+
+
+def time_plain(sample, workload: str, layout_name: str, flags: int, steps: int, warmup: int, tune) -> dict:
+    """One plain step per launch over the whole sample, inputs resident in
+    HBM: W warm-up launches, then back-to-back launches for at least 500 ms
+    more (clocks settle; nothing idles the GPU before the timed region),
+    then `steps` launches between two events on the launch stream."""
+    import torch
+    from paper_2409_09228_amd import kf as K
+    layout = parse_layout(layout_name)
+    geom = int(sample["geom"][0])
+    st = K.stage_sample(sample, layout)
+    n = st["n"]
+    updates = int(sample["nlay"].sum())
+    par_out = torch.empty_like(st["par"])
+    cov_out = torch.empty_like(st["cov"])
+    chi2 = torch.empty(n, dtype=torch.float32, device="cuda")
+    status = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    step = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
+                          out=(par_out, cov_out), chi2=chi2, status=status, nlay=st["nlay"], layout=layout,
+                          flags=flags, tune=tune, stream=stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(warmup):
+        step()
+    warm = warmup
+    torch.cuda.synchronize()
+    t_w = time.perf_counter()
+    while time.perf_counter() - t_w < 0.5:
+        for _ in range(20):
+            step()
+        warm += 20
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / steps
+    ok = int(((status & 0xFF) == 0).sum().item())
+    # diagnostics only (not used above): per-launch spread, events between launches
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(min(steps, 50) + 1)]
+    ev[0].record(stream)
+    for j in range(len(ev) - 1):
+        step()
+        ev[j + 1].record(stream)
+    ev[-1].synchronize()
+    per = sorted(ev[j].elapsed_time(ev[j + 1]) for j in range(len(ev) - 1))
+    L = int(sample["hit_pos"].shape[0])
+    config = {"workload": workload, "tracks": n, "layers": L, "updates_per_step": updates,
+              "nominal_updates_per_step": n * L, "layout": layout_name, "precision_flags": flags,
+              "tracks_per_s": round(n * steps / (ms / 1e3), 1), "ok_tracks": ok,
+              "warmup_launches": warm,
+              "warmup_note": "the W launches asked for, then back-to-back launches for >= 0.5 s more",
+              "host_wall_s": round(wall, 4), "launch_ms_mean": round(ms_step, 4),
+              "per_launch_events_ms": {"median": round(per[len(per) // 2], 4), "min": round(per[0], 4),
+                                       "max": round(per[-1], 4),
+                                       "note": "diagnostic: each launch between its own pair of events, "
+                                               "which adds a gap per launch; the timed figure is "
+                                               "launch_ms_mean (back-to-back launches)"}}
+    return {"value": updates * steps / (ms / 1e3), "ms_step": ms_step, "config": config,
+            "roofline": plain_roofline(geom, n, updates, ms_step, workload, layout_name, flags, st["nlay"] is None),
+            "staged": st, "outputs": (par_out, cov_out, chi2, status), "tune": tune}
 
 
 def time_launches(fn, steps: int, stream):
@@ -541,7 +783,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="p2z_100x9600")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--layout", default="soa")
     ap.add_argument("--flags", type=int, default=0)
     ap.add_argument("--block", type=int, default=None,
@@ -549,7 +791,10 @@ def main(argv=None):
     ap.add_argument("--tpt", type=int, default=None, help="tracks per thread (default 1)")
     ap.add_argument("--sched", type=int, default=None, help="batched form: 0 dynamic queue, 1 static round-robin")
     ap.add_argument("--waves-mult", type=int, default=None, help="batched form: grid in units of resident blocks")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU baseline and per-output precision error)")
+    ap.add_argument("--no-p2r", action="store_true",
+                    help="default workload: skip the barrel (p2r_100x9600) line beside it")
     ap.add_argument("--no-baseline", action="store_true", help="batched form: skip the per-bucket launches")
     ap.add_argument("--autotune", action="store_true",
                     help="batched and plain forms: search the launch shape and layout first, then time the winner")
@@ -621,129 +866,40 @@ def main(argv=None):
         args.block, args.layout = c["block"], c["layout"]
         tuned = {"config": c, "search_s": round(time.perf_counter() - t0, 1), "candidates": len(res["tried"]),
                  "worst_ms": round(max(t for _, t in res["tried"]), 4)}
-    layout = parse_layout(args.layout)
-    geom = int(sample["geom"][0])
-    st = K.stage_sample(sample, layout)
-    n = st["n"]
-    updates = int(sample["nlay"].sum())
-    par_out = torch.empty_like(st["par"])
-    cov_out = torch.empty_like(st["cov"])
-    chi2 = torch.empty(n, dtype=torch.float32, device="cuda")
-    status = torch.empty(n, dtype=torch.int32, device="cuda")
     args.block, args.tpt = args.block or 256, args.tpt or 1
-    tune = (args.block, args.tpt)
-    stream = torch.cuda.current_stream()
-
-    step_prealloc = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
-                                   st["bz"], n, out=(par_out, cov_out), chi2=chi2, status=status,
-                                   nlay=st["nlay"], layout=layout, flags=args.flags, tune=tune, stream=stream)
-
-    # warm-up: W steps, and at least 500 ms of GPU work so that clocks have
-    # settled; the timed region follows it directly (no other GPU work or
-    # idle time in between)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    for _ in range(args.warmup):
-        step_prealloc()
-    torch.cuda.synchronize()
-    t_w = time.perf_counter()
-    while time.perf_counter() - t_w < 0.5:
-        for _ in range(20):
-            step_prealloc()
-        torch.cuda.synchronize()
-    # timed region: K back-to-back launches between two events on the launch
-    # stream; the average launch duration is the interval over K
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step_prealloc()
-    e1.record(stream)
-    e1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_step = ms / args.steps
-    ok = int(((status & 0xFF) == 0).sum().item())
-    value = updates * args.steps / (ms / 1e3)
-    kernel_ms = ms_step
-    # diagnostics only (not used above): per-launch spread, events between launches
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(min(args.steps, 50) + 1)]
-    ev[0].record(stream)
-    for j in range(len(ev) - 1):
-        step_prealloc()
-        ev[j + 1].record(stream)
-    ev[-1].synchronize()
-    per = sorted(ev[j].elapsed_time(ev[j + 1]) for j in range(len(ev) - 1))
-
-    flops = FLOPS_PER_UPDATE[geom] * updates
-    flops_c = FLOPS_CHARGED_PER_UPDATE[geom] * updates
-    bytes_ = TRACK_BYTES * n + LAYER_BYTES * updates
-    sec = kernel_ms / 1e3
-    hbm = bytes_ / sec / 1e9
-    tfl = flops / sec / 1e12
-    tfl_c = flops_c / sec / 1e12
-    fr_hbm = hbm / HBM_PEAK_GBS
-    fr_alu = tfl / FP32_PEAK_TFLOPS
-    fr_valu = tfl_c / FP32_PEAK_TFLOPS
-    # Roofline: the larger of the HBM fraction (algorithmic bytes) and the
-    # VALU fraction (algorithmic flops, transcendentals charged) binds; the
-    # other side is reported alongside.
-    intensity = flops / bytes_
-    ridge = FP32_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if fr_hbm >= fr_valu:
-        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(fr_hbm, 4), "traffic": None}
-    else:
-        roof = {"bound": "alu", "achieved": round(tfl_c, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(fr_valu, 4), "traffic": None}
-    roof["intensity_flop_per_byte"] = round(intensity, 2)
-    roof["ridge_flop_per_byte"] = round(ridge, 2)
-    traffic = measured_traffic(args.workload, args.layout, args.flags)
-    if traffic is not None:
-        roof["traffic"] = traffic
-    roof["flops_per_update"] = FLOPS_PER_UPDATE[geom]
-    roof["flops_per_update_transcendentals_charged"] = FLOPS_CHARGED_PER_UPDATE[geom]
-    roof["valu_achieved_TFLOPs_charged"] = round(tfl_c, 3)
-    roof["valu_frac_charged"] = round(fr_valu, 4)
-    roof["valu_frac_charged_of_nonpacked_peak"] = round(tfl_c / FP32_PEAK_NONPACKED_TFLOPS, 4)
-    roof["alu_achieved_TFLOPs"] = round(tfl, 3)
-    roof["alu_frac"] = round(fr_alu, 4)
-    roof["frac_of_nonpacked_fp32_peak"] = round(tfl / FP32_PEAK_NONPACKED_TFLOPS, 4)
-    roof["hbm_algorithmic_bytes_per_launch"] = int(bytes_)
-    roof["hbm_achieved_GBs"] = round(hbm, 1)
-    roof["hbm_frac"] = round(fr_hbm, 4)
-    roof["kernel"] = "kf_step_kernel<%d,%d,%s,%s>" % (geom, {0: 0, 1: 1, 3: 2}.get(args.flags, 0), args.layout,
-                                                   "streamed" if st["nlay"] is None else "counted")
-    roof["kernel_source_sha256"] = kernel_source_digest()
-
+    head = time_plain(sample, args.workload, args.layout, args.flags, args.steps, args.warmup,
+                      (args.block, args.tpt))
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": round(head["value"], 1),
         "unit": "track-layer updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(head["ms_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if args.flags == 0 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "tracks": n, "layers": int(sample["hit_pos"].shape[0]),
-                   "updates_per_step": updates, "nominal_updates_per_step": n * int(sample["hit_pos"].shape[0]), "layout": args.layout, "precision_flags": args.flags,
-                   "block": args.block, "tracks_per_thread": args.tpt,
-                   "tracks_per_s": round(n * args.steps / (ms / 1e3), 1), "ok_tracks": ok,
-                   "host_wall_s": round(wall, 4), "launch_ms_mean": round(kernel_ms, 4),
-                   "per_launch_events_ms": {"median": round(per[len(per) // 2], 4), "min": round(per[0], 4),
-                                            "max": round(per[-1], 4),
-                                            "note": "diagnostic: each launch between its own pair of events, "
-                                                    "which adds a gap per launch; the timed figure is "
-                                                    "launch_ms_mean (back-to-back launches)"},
-                   "autotune": tuned},
-        "roofline": roof,
+        "config": dict(head["config"], block=args.block, tracks_per_thread=args.tpt, autotune=tuned),
+        "roofline": head["roofline"],
     }
+    # the barrel form beside the headline plane form: same launch shape, same
+    # timing procedure, its own roofline
+    if not args.no_p2r and args.workload == DEFAULT_WORKLOAD and args.flags == 0:
+        r_sample = S.generate(P2R_WORKLOAD)
+        r = time_plain(r_sample, P2R_WORKLOAD, args.layout, 0, args.steps, args.warmup, (args.block, args.tpt))
+        out["p2r"] = {"workload": P2R_WORKLOAD, "value": round(r["value"], 1), "unit": "track-layer updates/s",
+                      "ms_per_step": round(r["ms_step"], 4), "config": r["config"], "roofline": r["roofline"]}
+    else:
+        r_sample, r = None, None
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sample, args.cpu_tracks, args.cpu_seconds)
+        # the oracle leg: the FP64 oracle timed on the host's cores, and its
+        # results on sampled tracks against the GPU's (per-output error)
+        leg = oracle_leg(sample, args, head, r_sample, r)
+        out["cpu_baseline"] = leg["cpu_baseline"]
+        out["precision_error"] = leg["precision_error"]
     print(json.dumps(out), flush=True)
     return 0
 

@@ -120,7 +120,9 @@ enum {
 enum {
   KF_S_NONFINITE = 1,       /* a NaN or Inf entered or came out of the update */
   KF_S_NOT_PD = 2,          /* S failed Sylvester's criterion */
-  KF_S_NO_CROSSING = 4,     /* the helix never reaches the cylinder */
+  KF_S_NO_CROSSING = 4,     /* the helix never reaches the surface: a cylinder beyond its
+                               reach, or a plane parallel to its direction
+                               (|cos theta| < 1e-6) */
   KF_S_NEWTON_RESIDUAL = 8, /* the cylinder iteration ended off the surface */
   KF_S_BAD_HITS = 16        /* kf_propagate_update_batched: the track's hit rows fall
                                outside [0, n_hits); the track is left as it came in */
@@ -160,7 +162,8 @@ enum {
  *
  * The plane is reached after the transverse path s = (z_l - z) tan(theta);
  * the propagated z equals z_l exactly and the covariance's z row and column
- * become zero (a plane fixes z).
+ * become zero (a plane fixes z).  A track within 1e-6 rad of theta = pi/2
+ * (|cos theta| < 1e-6) runs parallel to the planes: KF_S_NO_CROSSING.
  */
 kf_status_t kf_propagate_update_z(
     const float* par_in, const float* cov_in, float* par_out, float* cov_out,

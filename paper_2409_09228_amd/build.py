@@ -39,19 +39,33 @@ FLAGS = [
 ]
 
 
-def build(resource_usage: bool = False, verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = [HIPCC, *FLAGS, *srcs, "-o", LIB + ".tmp"]
-    if resource_usage:
-        cmd.insert(1, "-Rpass-analysis=kernel-resource-usage")
+def _run(cmd, verbose: bool, show_stderr: bool):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libkf.so")
-    if resource_usage or verbose:
+    if show_stderr:
         sys.stderr.write(r.stderr)
+
+
+def build(resource_usage: bool = False, verbose: bool = False, jobs: int | None = None) -> str:
+    """Compile every source to an object file (in parallel: the translation
+    units share no device code, so no relocatable device code is needed),
+    then link the shared library."""
+    import tempfile
+    from concurrent.futures import ThreadPoolExecutor
+    compile_flags = [f for f in FLAGS if f not in ("-shared", "-Wl,--no-undefined")]
+    if resource_usage:
+        compile_flags = ["-Rpass-analysis=kernel-resource-usage", *compile_flags]
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    with tempfile.TemporaryDirectory(prefix="kf_build_") as tmp:
+        objs = [os.path.join(tmp, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [[HIPCC, *compile_flags, "-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+        with ThreadPoolExecutor(jobs) as ex:
+            list(ex.map(lambda c: _run(c, verbose, resource_usage or verbose), cmds))
+        _run([HIPCC, *FLAGS, *objs, "-o", LIB + ".tmp"], verbose, verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -659,8 +659,11 @@ template <int GEOM, bool ZIN, class T>
 __device__ __forceinline__ uint32_t propagate(const T p[6], const T C[21], DirT<T>& d, T target, T b, T q[6],
                                               T Pt[21]) {
   if (GEOM == 0) {
+    // a track parallel to the planes (theta within 1e-6 rad of pi/2) never
+    // reaches one; theta does not change on the way, so the entering cosine decides
+    const uint32_t f = fabs_t(d.ct) < T(1e-6) ? S_NO_CROSSING : 0u;
     propagate_z<ZIN, T>(p, C, d, target, b, q, Pt);
-    return 0u;
+    return f;
   }
   return propagate_r<T>(p, C, d, target, b, q, Pt);
 }

@@ -19,8 +19,6 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkf.so")
-# another build of the same library (a variant's timing) may be named here
-LIB_PATH = os.environ.get("KF_LIB", LIB_PATH)
 
 KF_OK = 0
 KF_SOA = 0
@@ -153,13 +151,22 @@ def _check(rc: int, where: str):
         raise KFError(rc, where)
 
 
-def _require_cuda(*ts):
+def _require_cuda(*ts, real=None):
+    """GPU tensors, contiguous, of the element type the C ABI reads for them:
+    `real` (float32, or float64 for the FP64 entry points) arrays, int32
+    layer counts and status words, int64 hit offsets, uint8 geometry codes
+    (a float64 tensor would otherwise be read as pairs of floats)."""
+    import torch
+    real = torch.float32 if real is None else real
     for t in ts:
         if t is not None:
             if not t.is_cuda:
                 raise ValueError("libkf works on GPU tensors only")
             if not t.is_contiguous():
                 raise ValueError("tensors must be contiguous")
+            if t.dtype not in (real, torch.int32, torch.int64, torch.uint8):
+                raise ValueError(f"libkf reads {real} arrays here (int32/int64/uint8 for counts, offsets "
+                                 f"and codes), not {t.dtype}")
 
 
 def array_floats(n_elem: int, n_layers: int, n: int, layout) -> int:
@@ -408,7 +415,7 @@ class StepLauncherF64:
 
     def __init__(self, st: dict, flags: int = 0, tune=None, stream=None, out=None, nlay=True):
         import torch
-        _require_cuda(st["par"], st["cov"], st["hit_pos"], st["hit_cov"])
+        _require_cuda(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], real=torch.float64)
         n = st["n"]
         dev = st["par"].device
         self.par_out, self.cov_out = out if out is not None else (torch.empty_like(st["par"]),
@@ -737,19 +744,25 @@ def _make_autograd():
             L = int(np.asarray(layer_z).shape[0])
             every = 1 if checkpoint is True else int(checkpoint)
             ck = checkpoint_buffer(n, L, layout, par.device, every) if checkpoint else None
+            for t in (par, hit_pos, cov, hit_cov):
+                if t.dtype != torch.float32:
+                    raise ValueError("KFChi2 takes float32 tensors")
             _, _, chi2, status = propagate_update(0, par, cov, hit_pos, hit_cov, layer_z, bz, n, nlay=nlay,
                                                   layout=layout, ckpt=ck, ckpt_every=every)
-            ctx.st = {"par": par, "cov": cov, "hit_pos": hit_pos, "hit_cov": hit_cov, "layers": layer_z,
-                      "n": n, "bz": bz, "layout": layout}
-            ctx.save_for_backward(status)
+            ctx.meta = {"layers": layer_z, "n": n, "bz": bz, "layout": layout}
+            # saved through autograd, so that an in-place change of an input
+            # between forward and backward raises instead of giving wrong
+            # gradients (the backward re-reads the inputs)
+            ctx.save_for_backward(par, cov, hit_pos, hit_cov, status)
             ctx.ckpt = ck
             ctx.every = every
             return chi2
 
         @staticmethod
         def backward(ctx, grad_chi2):
-            (status,) = ctx.saved_tensors
-            gh, gp, _ = chi2_backward_z(ctx.st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt,
+            par, cov, hit_pos, hit_cov, status = ctx.saved_tensors
+            st = dict(ctx.meta, par=par, cov=cov, hit_pos=hit_pos, hit_cov=hit_cov)
+            gh, gp, _ = chi2_backward_z(st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt,
                                         ckpt_every=ctx.every)
             return gp, gh, None, None, None, None, None, None, None
 

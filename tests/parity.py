@@ -14,6 +14,14 @@ order of the kernels:
   chi-square                     |d chi2| / max(chi2, 1) <= 5e-3
   status words                   identical (flags and layers applied)
 
+The FP32 build of the oracle is itself pinned (tests/test_oracle_f32.py) to
+an independent FP32-versus-FP64 calibration of the plane sample.  It can
+only tighten a gate on the 20-layer samples (assert_two_sided) and loosen
+one for longer inputs by at most CEILING times (calibrated).  On cylinders
+its closed-form crossing is ill-conditioned in float for large radii of
+curvature (the centre distance and the radius nearly cancel), so there its
+error is large and the ceiling is what binds.
+
 For the barrel the propagated covariance has an exactly null radial
 direction, so x and y are normalised by the transverse position variance
 P_xx + P_yy instead of their own (possibly vanishing) variances; on planes
@@ -92,11 +100,28 @@ def metrics(ref, got, geom: int, mask=None) -> dict:
     return out
 
 
+# Longest gates any input may get: FP32 rounding grows about linearly with
+# the path, and the longest layer table (64) is 3.2x the 20 layers the fixed
+# gates were calibrated on.
+CEILING = 3.0
+
+
 def calibrated(tol: dict, f32_metrics: dict, factor: float = 2.0) -> dict:
     """Gates for inputs outside the calibration sample (e.g. 64 planes, where
-    FP32 rounding accumulates over longer paths): the fixed gate, or twice
-    the error the FP32 build of the oracle makes on the same input."""
-    return {k: max(v, factor * f32_metrics[k]) for k, v in tol.items()}
+    FP32 rounding accumulates over longer paths): twice the error the FP32
+    build of the oracle makes on the same input, but never below the fixed
+    gate and never above CEILING times it."""
+    return {k: min(CEILING * v, max(v, factor * f32_metrics[k])) for k, v in tol.items()}
+
+
+def assert_two_sided(m: dict, f32_metrics: dict, tol: dict, what: str = "", factor: float = 2.0):
+    """On the calibration-like samples the GPU must also stay within twice
+    the error of the FP32 build of the oracle on the same input, metric by
+    metric (an FP32 evaluation is what the kernels are; a tenth of the fixed
+    gate is the floor below which rounding noise is not compared)."""
+    for k, v in tol.items():
+        lim = max(factor * f32_metrics[k], 0.1 * v)
+        assert m[k] <= lim, f"{what}: {k} = {m[k]:.3g} exceeds twice the FP32 oracle's {f32_metrics[k]:.3g}"
 
 
 def assert_within(m: dict, tol: dict, what: str = ""):

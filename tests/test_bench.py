@@ -38,3 +38,26 @@ def test_algorithmic_bytes_per_update():
     assert abs((bench.TRACK_BYTES / 20 + bench.LAYER_BYTES) - 47.2) < 1e-9
     assert bench.FLOPS_CHARGED_PER_UPDATE[0] > bench.FLOPS_PER_UPDATE[0]
     assert bench.FLOPS_CHARGED_PER_UPDATE[1] > bench.FLOPS_PER_UPDATE[1]
+
+
+def test_output_errors_report_each_output():
+    """A known perturbation of an FP64 result shows up in its own entry of
+    the per-output report and nowhere else."""
+    import oracle as O
+    s = S.subset(S.generate("p2z_1x8192", n_events=1), np.arange(300))
+    ref = O.run_sample(s)
+    got = [x.copy() for x in ref]
+    got[0][:, 3] += 2e-7                     # kappa: 2e-7 over the smallest |kappa| (>= the 0.1 floor)
+    got[0][:, 4] += 2 * np.pi                # phi modulo 2 pi: no error
+    e = bench.output_errors(ref, tuple(got), 0)
+    want = 2e-7 / np.abs(ref[0][:, 3]).min()
+    assert abs(e["kappa"] - want) < 5e-3 * want and e["phi"] < 1e-12   # reported to 3 digits
+    assert e["x"] == e["y"] == e["z"] == e["theta"] == 0.0
+    assert e["cov_corr"] == 0.0 and e["chi2_rel"] == 0.0 and e["status_mismatch"] == 0
+    got[2] = got[2] * (1 + 1e-4)
+    assert abs(bench.output_errors(ref, tuple(got), 0)["chi2_rel"] - 1e-4) < 2e-5
+
+
+def test_cpu_identity_is_a_dict():
+    info = bench.cpu_identity()
+    assert isinstance(info, dict)

@@ -4,12 +4,18 @@ in test_oracle_pins), central finite differences (h = 1e-4) of the FP64
 oracle, the closed form on the last layer, finite differences of the GPU's
 own forward, and the torch.autograd.Function.
 
-Tolerance: per track, max |g_gpu - g_ref| / max |g_ref|.  The residual
-r = m - q is a ~0.01 cm difference of positions of tens of cm, so any float
-evaluation of the filter carries ~1e-4 relative error in its states into the
-gradient 2 S^-1 r at the 1e-3 level: the FP32 build of the oracle's own
-gradient shows 2.5e-3 (hits) and 5.7e-3 (seed parameters) at worst on these
-samples.  The gate is max(1e-3, twice that FP32 error on the same input)."""
+Error metric: element by element, |g_gpu - g_ref| / max(|g_ref|, s_col),
+where s_col is the RMS over tracks of the reference's column (one column per
+seed parameter, and per layer and coordinate of the hits), so that every
+entry is held to its own column's scale and small entries are not excused
+by a large neighbour.  Gate TOL_GRAD = 1e-2.  Derivation: the residual
+r = m - q is a ~0.01 cm difference of positions of tens of cm, so one float
+rounding of a position (~4e-6 cm at 50 cm) moves the gradient 2 S^-1 r
+(S ~ 2e-4 cm^2) by ~0.04 against a column scale of ~250, i.e. 1.5e-4; the
+states carry some tens of such roundings through 20 layers, giving a few
+1e-3 (the FP32 build of the oracle shows 6.2e-3 on hits, 2.9e-3 on seed
+parameters).  On top of the fixed gate the GPU must stay within twice the
+FP32 oracle's error on the same input (assert_two_sided)."""
 import numpy as np
 import pytest
 
@@ -20,18 +26,35 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-TOL_GRAD = 1e-3
+TOL_GRAD = 1e-2
 
 
-def _gates(s, w=None):
-    """Reference gradient, and gates sized by the FP32 build of the same gradient."""
-    rh, rp = O.grad_chi2(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"], w=w,
-                         nlay=s["nlay"])
-    fh, fp = O.grad_chi2(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"], w=w,
-                         nlay=s["nlay"], precision="f32")
-    th = max(TOL_GRAD, 2 * _rel(fh.transpose(1, 0, 2), rh.transpose(1, 0, 2)))
-    tp = max(TOL_GRAD, 2 * _rel(fp, rp))
-    return rh.transpose(1, 0, 2), rp, th, tp
+def _col_scale(ref, axis=0):
+    return np.sqrt(np.mean(ref ** 2, axis=axis, keepdims=True))
+
+
+def _err(got, ref, scale=None):
+    """Largest element-wise error floored at the column scale (RMS over the
+    tracks of axis 0, or the given scale)."""
+    sc = _col_scale(ref) if scale is None else scale
+    return float((np.abs(got - ref) / np.maximum(np.abs(ref), sc)).max())
+
+
+def _reference(s, w=None):
+    """FP64 reference gradient [track][layer][3], [track][6], and the FP32
+    build's errors against it (for the two-sided check)."""
+    args = (0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"])
+    rh, rp = O.grad_chi2(*args, w=w, nlay=s["nlay"])
+    fh, fp = O.grad_chi2(*args, w=w, nlay=s["nlay"], precision="f32")
+    rh, fh = rh.transpose(1, 0, 2), fh.transpose(1, 0, 2)
+    return rh, rp, _err(fh, rh), _err(fp, rp)
+
+
+def _check(gh, gp, rh, rp, fh_err, fp_err, what=""):
+    eh, ep = _err(gh, rh), _err(gp, rp)
+    print(what, "hit", eh, "(fp32 oracle", fh_err, ") par", ep, "(fp32 oracle", fp_err, ")")
+    assert eh <= TOL_GRAD and ep <= TOL_GRAD, (eh, ep)
+    assert eh <= max(2 * fh_err, 0.1 * TOL_GRAD) and ep <= max(2 * fp_err, 0.1 * TOL_GRAD), (eh, fh_err, ep, fp_err)
 
 
 @pytest.fixture(scope="module")
@@ -64,22 +87,12 @@ def _fwd_bwd(kf, sample, layout=None, checkpoint=True, w=None, every=1):
     return ghl.astype(np.float64), gpl, c2.cpu().numpy(), ss.cpu().numpy(), gc
 
 
-def _rel(got, ref):
-    """Per track: max |diff| / max |ref| over that track's gradient entries."""
-    scale = np.maximum(np.abs(ref).max(axis=tuple(range(1, ref.ndim))), 1e-30)
-    return (np.abs(got - ref).max(axis=tuple(range(1, ref.ndim))) / scale).max()
-
-
 @pytest.mark.parametrize("checkpoint", [True, False])
 def test_gradient_matches_fp64_reference(kf, checkpoint):
     s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(512))
     w = np.random.default_rng(3).uniform(0.5, 2.0, 512)
     gh, gp, _, st, _ = _fwd_bwd(kf, s, checkpoint=checkpoint, w=w)
-    rh, rp, th, tp = _gates(s, w)
-    eh = _rel(gh, rh)
-    ep = _rel(gp, rp)
-    print("hit", eh, th, "par", ep, tp)
-    assert eh <= th and ep <= tp
+    _check(gh, gp, *_reference(s, w), what=f"checkpoint={checkpoint}")
 
 
 def test_gradient_matches_central_differences_h1e4(kf):
@@ -101,9 +114,8 @@ def test_gradient_matches_central_differences_h1e4(kf):
         for a in range(3):
             e = np.zeros_like(s["hit_pos"]); e[k, :, a] = h
             fh[:, k, a] = (chi(s["par"], s["hit_pos"] + e) - chi(s["par"], s["hit_pos"] - e)) / (2 * h)
-    _, _, th, tp = _gates(s)
-    print(_rel(gh, fh), th, _rel(gp, fp), tp)
-    assert _rel(gh, fh) <= th + 1e-4 and _rel(gp, fp) <= tp + 1e-4
+    print(_err(gh, fh), _err(gp, fp))
+    assert _err(gh, fh) <= TOL_GRAD and _err(gp, fp) <= TOL_GRAD
 
 
 def test_checkpoint_and_recompute_agree(kf):
@@ -130,10 +142,9 @@ def test_segment_checkpoints_agree(kf, every):
     b = _fwd_bwd(kf, s, every=every)
     np.testing.assert_array_equal(a[2], b[2])
     np.testing.assert_array_equal(a[3], b[3])
-    rh, rp, th, tp = _gates(s)
-    print(every, _rel(b[0], rh), th, _rel(b[1], rp), tp)
-    assert _rel(b[0], rh) <= th and _rel(b[1], rp) <= tp
-    assert _rel(b[0], a[0]) <= th and _rel(b[1], a[1]) <= tp
+    rh, rp, fh_err, fp_err = _reference(s)
+    _check(b[0], b[1], rh, rp, fh_err, fp_err, what=f"every {every}")
+    assert _err(b[0], a[0], _col_scale(rh)) <= TOL_GRAD and _err(b[1], a[1], _col_scale(rp)) <= TOL_GRAD
 
 
 @pytest.mark.parametrize("layout", ["aos", "aosoa64"])
@@ -151,16 +162,17 @@ def test_last_layer_closed_form(kf):
     with S_L and r_L from the oracle's state one layer earlier."""
     s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(64))
     gh, _, _, _, _ = _fwd_bwd(kf, s)
-    _, _, th, _ = _gates(s)
     L = s["hit_pos"].shape[0]
     po, co, _, _ = O.run(0, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], s["layer_z"], s["bz"],
                          nlay=np.full(64, L - 1, np.int32))
+    ref = np.zeros((64, 3))
     for i in range(64):
         pt, F, _ = O.propagate(0, po[i], s["layer_z"][-1], s["bz"])
         Pt = F @ O.unpack_sym(co[i]) @ F.T
         Sm = Pt[:3, :3] + O.unpack_sym(s["hit_cov"][-1, i])
-        ref = 2 * np.linalg.solve(Sm, s["hit_pos"][-1, i] - pt[:3])
-        assert np.abs(gh[i, -1] - ref).max() <= th * np.abs(gh[i]).max()
+        ref[i] = 2 * np.linalg.solve(Sm, s["hit_pos"][-1, i] - pt[:3])
+    print(_err(gh[:, -1], ref))
+    assert _err(gh[:, -1], ref) <= TOL_GRAD
 
 
 def test_matches_finite_differences_of_gpu_forward(kf):
@@ -192,15 +204,17 @@ def test_failed_track_gradient_stops_at_its_layer(kf):
     assert np.all(gh[3, 5:] == 0.0)
     one = S.subset(s, np.array([3]))
     one["hit_pos"], one["hit_cov"], one["nlay"] = s["hit_pos"][:5, 3:4], s["hit_cov"][:5, 3:4], np.array([5], np.int32)
-    rh, rp, th, tp = _gates(one)
-    assert _rel(gh[3:4, :5], rh) <= th
-    assert _rel(gp[3:4], rp) <= tp
+    rh, rp, _, _ = _reference(one)
+    # column scales from the other tracks' reference gradients
+    full_h, full_p, _, _ = _reference(S.subset(s, np.delete(np.arange(128), 3)))
+    assert _err(gh[3:4, :5], rh, _col_scale(full_h[:, :5])) <= TOL_GRAD
+    assert _err(gp[3:4], rp, _col_scale(full_p)) <= TOL_GRAD
 
 
 def test_autograd_function(kf):
     s = S.subset(S.generate("p2z_64x9600", n_events=1), np.arange(300))
     w = np.linspace(0.5, 1.5, 300)
-    rh, rp, th, tp = _gates(s, w)
+    rh, rp, fh_err, fp_err = _reference(s, w)
     st = kf.stage_sample(s)
     par = st["par"].clone().requires_grad_(True)
     hp = st["hit_pos"].clone().requires_grad_(True)
@@ -212,8 +226,7 @@ def test_autograd_function(kf):
         loss.backward()
         gp = kf.from_soa_tensor(par.grad).astype(np.float64)
         gh = hp.grad.cpu().numpy().transpose(2, 0, 1).astype(np.float64)
-        assert _rel(gp, rp) <= tp
-        assert _rel(gh, rh) <= th
+        _check(gh, gp, rh, rp, fh_err, fp_err, what=f"autograd checkpoint={ckpt}")
 
 
 def test_64bit_addressing_matches_32bit(kf):
@@ -256,8 +269,5 @@ def test_full_size_sampled(kf):
     idx = np.sort(rng.choice(n, 300, replace=False))
     idx[-1] = n - 1
     sub = S.subset(s, idx)
-    rh, rp, th, tp = _gates(sub)
-    eh, ep = _rel(gh[idx], rh), _rel(gp[idx], rp)
-    print("hit", eh, th, "par", ep, tp)
-    assert eh <= th and ep <= tp
+    _check(gh[idx], gp[idx], *_reference(sub), what="full size")
     assert np.all((st & 0xFF) == 0)

@@ -183,3 +183,29 @@ def test_workspace_too_small_is_rejected(kf, uneven):
     with pytest.raises(kf.KFError) as e:
         kf.run_batched(st, workspace=small)
     assert e.value.code == 7
+
+
+def test_64bit_hit_rows_match_32bit(kf, uneven):
+    """Ragged hit arrays of 180M rows (4.32 GB of covariances, past the 4 GiB
+    a 32-bit buffer offset reaches) put the persistent kernel in its 64-bit
+    address form.  20,000 tracks whose rows sit at the end of those arrays
+    (the rows before them zero) give, bit for bit, what the same tracks give
+    with their rows in arrays of their own (the 32-bit form)."""
+    sub = S.subset(uneven, np.arange(20000))
+    st = kf.stage_batched(sub, kf.AOS)
+    small = _logical(kf, st, kf.run_batched(st))
+    H = st["hit_pos"].shape[0]
+    rows = 180_000_000
+    assert rows * 24 >= 1 << 32 and rows > H
+    start = rows - H
+    hp = torch.zeros(rows, 3, device="cuda")
+    hc = torch.zeros(rows, 6, device="cuda")
+    hp[start:] = st["hit_pos"]
+    hc[start:] = st["hit_cov"]
+    st2 = dict(st, hit_pos=hp, hit_cov=hc, hit_offset=st["hit_offset"] + start)
+    big = _logical(kf, st2, kf.run_batched(st2))
+    for k in range(4):
+        np.testing.assert_array_equal(big[k], small[k])
+    del hp, hc, st2
+    kf.release_graphs()
+    torch.cuda.empty_cache()

@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2409_09228_amd import synth as S
-from parity import TOL_F32, TOL_PRECISION, assert_within, calibrated, metrics
+from parity import TOL_F32, TOL_PRECISION, assert_two_sided, assert_within, calibrated, metrics
 
 pytestmark = pytest.mark.gpu
 
@@ -47,9 +47,12 @@ def test_p2z_8192_all_layouts(kf, layout):
     s = S.generate("p2z_1x8192")
     lay = _layout(kf, layout)
     got = _gpu_run(kf, s, lay)
-    m = metrics(_oracle(s), got, 0)
-    print(layout, m)
+    ref = _oracle(s)
+    m = metrics(ref, got, 0)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), 0)
+    print(layout, m, "fp32 oracle", f32)
     assert_within(m, TOL_F32, f"p2z layout {layout}")
+    assert_two_sided(m, f32, TOL_F32, f"p2z layout {layout}")
     assert np.all(got[3] == 20 << 16)
 
 
@@ -59,8 +62,10 @@ def test_p2r_9600(kf, layout):
     got = _gpu_run(kf, s, _layout(kf, layout))
     ref = _oracle(s)
     m = metrics(ref, got, 1)
-    print(m)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), 1)
+    print(m, "fp32 oracle", f32)
     assert_within(m, TOL_F32, "p2r")
+    assert_two_sided(m, f32, TOL_F32, "p2r")
     np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
 
 
@@ -90,8 +95,10 @@ def test_full_size_sampled(kf, name, geom):
     ref = _oracle(sub)
     gsub = tuple(x[idx] for x in got)
     m = metrics(ref, gsub, geom)
-    print(name, m)
+    f32 = metrics(ref, O.run_sample(sub, precision="f32"), geom)
+    print(name, m, "fp32 oracle", f32)
     assert_within(m, TOL_F32, name)
+    assert_two_sided(m, f32, TOL_F32, name)
     assert np.all((got[3] & 0xFF) == 0)
     np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
     # sample means over all tracks vs the oracle's means over the same sample:
@@ -171,6 +178,68 @@ def test_p2r_no_crossing_matches_oracle(kf):
     ref = _oracle(s)
     np.testing.assert_array_equal(got[3], ref[3])
     assert np.all((ref[3] & 0xFF) == O.ST_NO_CROSSING)
+
+
+def test_plane_parallel_track_and_steep_tracks(kf):
+    """theta = pi/2 (the float32 value nearest it) never reaches a plane:
+    KF_S_NO_CROSSING on the first layer, state returned untouched, as in the
+    oracle.  Tracks at theta = pi/2 -+ 0.3 (far outside the sample's
+    [0.4, 1.2]; beyond pi/2 the planes lie behind and are reached backwards)
+    cross them after transverse paths of up to 3.2 times the plane distance
+    and match the oracle at the length-scaled gates."""
+    rng = np.random.default_rng(5)
+    n = 192
+    s = S.subset(S.generate("p2z_1x8192"), np.arange(n))
+    truth = s["truth"].copy()
+    truth[:64, 5] = np.float32(np.pi / 2)
+    truth[64:128, 5] = np.pi / 2 - 0.3
+    truth[128:, 5] = np.pi / 2 + 0.3
+    s["truth"] = truth
+    s["par"] = truth.copy()
+    hp = np.stack([S.truth_cross_plane(truth, zk, s["bz"]) for zk in s["layer_z"]])
+    s["hit_pos"] = np.where(np.isfinite(hp), hp + rng.normal(0, 0.01, hp.shape), 0.0)
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    assert np.all(ref[3][:64] == O.ST_NO_CROSSING)
+    assert np.all(ref[3][64:] == 20 << 16)
+    np.testing.assert_array_equal(got[0][:64], s["par"][:64].astype(np.float32))
+    ok = np.arange(n) >= 64
+    m = metrics(ref, got, 0, mask=ok)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), 0, mask=ok)
+    print(m, "fp32 oracle", f32)
+    assert_within(m, calibrated(TOL_F32, f32), "steep tracks")
+
+
+def test_newton_residual_next_to_tangency(kf):
+    """Barrel tracks from the origin with radius of curvature R meet a
+    cylinder at 2R (1 - eps) at a nearly double root.  eps = 1e-5: the five
+    Newton steps end off the cylinder (residual ~2.24e-4 r^2 against the
+    2e-4 r^2 threshold), KF_S_NEWTON_RESIDUAL at that layer; eps = 1e-3:
+    they land.  Status words and frozen states as in the oracle, which takes
+    the same five-step decision in single precision."""
+    b = S.C_LIGHT * 3.8
+    n = 128
+    rng = np.random.default_rng(7)
+    truth = np.zeros((n, 6))
+    truth[:, 3] = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    truth[:, 4] = rng.uniform(-np.pi, np.pi, n)
+    truth[:, 5] = rng.uniform(0.5, 2.6, n)
+    R = 1.0 / b
+    for eps, flagged in ((1e-5, True), (1e-3, False)):
+        layers = np.array([20.0, 40.0, 2 * R * (1 - eps)])
+        hp = np.stack([S.truth_cross_cylinder(truth, rk, 3.8) for rk in layers])
+        assert np.all(np.isfinite(hp))
+        s = {"name": "tangent", "par": truth.copy(), "cov": S.diag_packed(6, 1e-4, n), "truth": truth,
+             "hit_pos": hp, "hit_cov": np.broadcast_to(S.diag_packed(3, 1e-4, 1)[None], (3, n, 6)).copy(),
+             "layer_z": layers, "layer_r": layers, "nlay": np.full(n, 3, np.int32),
+             "geom": np.full(n, 1, np.uint8), "bz": 3.8}
+        got = _gpu_run(kf, s)
+        ref = _oracle(s)
+        np.testing.assert_array_equal(got[3], ref[3])
+        want = (O.ST_NEWTON_RESIDUAL | (2 << 16)) if flagged else (3 << 16)
+        assert np.all(ref[3] == want), np.unique(ref[3])
+        assert_within(metrics(ref, got, 1), TOL_F32, f"tangent eps={eps}")
 
 
 def test_max_layers(kf):
