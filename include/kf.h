@@ -221,7 +221,12 @@ kf_status_t kf_propagate_update_r(
  *   n_cand        1 .. KF_MAX_CANDIDATES
  *   chi2_gate     the largest chi-square accepted (+inf: no gate; NaN is
  *                 KF_E_SHAPE)
- *   flags         0 (FP32 update)
+ *   flags         0 (FP32 update) or the precision bits of
+ *                 kf_propagate_update_z: KF_F_FP64_INVERSE takes every
+ *                 candidate's S^-1, the decision's chi-square, the gain and
+ *                 the update in FP64; KF_F_JOSEPH adds the Joseph covariance
+ *                 update (the form for tracks updated after several holes,
+ *                 whose plain FP32 covariance update cancels badly)
  *   chosen_out    [n_layers][n_tracks] int32 or NULL: the candidate used on
  *                 each layer processed, -1 for a hole (layers not processed
  *                 are left untouched)

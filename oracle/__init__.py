@@ -77,8 +77,8 @@ def lib():
         L.kfo_filter_record.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, d, d, d,
                                         i32, c_int, c_int]
         L.kfo_filter_record.restype = ctypes.c_int
-        L.kfo_gate_run.argtypes = [c_int, c_i64, c_int, c_int, d, c_dbl, i32, d, d, d, d, c_dbl, i32, d, d, d,
-                                   i32, i32, d, c_int, c_int]
+        L.kfo_gate_run.argtypes = [c_int, c_i64, c_int, c_int, d, c_dbl, i32, d, d, d, d, c_dbl, i32, c_int, d, d,
+                                   d, i32, i32, d, c_int, c_int]
         L.kfo_gate_run.restype = ctypes.c_int
         for fn in (L.kfo_run_f64, L.kfo_run_f32, L.kfo_propagate, L.kfo_update, L.kfo_grad_chi2,
                    L.kfo_grad_chi2_f32):
@@ -318,11 +318,11 @@ def smooth_sample(sample: dict, **kw):
 
 
 def gate_run(geom: int, par, cov, cand_pos, cand_cov, layers, bz: float, gate: float, nlay=None, forced=None,
-             precision: str = "f64", nthreads=None) -> dict:
+             joseph=False, precision: str = "f64", nthreads=None) -> dict:
     """The filter with hit selection among M candidate hits per layer: on
     every layer the candidate with the smallest update chi-square not above
-    `gate` updates the state, or none (a hole: the state is the prediction).
-    cand_pos [L, n, M, 3], cand_cov [L, n, M, 6]; forced [L, n] int (the
+    `gate` updates the state, or none (a hole: the state is the prediction);
+    joseph=True takes that update in Joseph form.  cand_pos [L, n, M, 3], cand_cov [L, n, M, 6]; forced [L, n] int (the
     choices to follow instead, -1 a hole).  Returns par [n, 6], cov [n, 21],
     chi2 [n], status [n], chosen [L, n] (-2 where a layer was not processed)
     and cand_chi2 [L, n, M] (NaN for candidates that take no part)."""
@@ -340,7 +340,7 @@ def gate_run(geom: int, par, cov, cand_pos, cand_cov, layers, bz: float, gate: f
     c = ctypes.c_double
     rc = lib().kfo_gate_run(int(geom), n, L, M, _p(layers, c), float(bz), _p(nl, ctypes.c_int32), _p(par, c),
                             _p(cov, c), _p(cand_pos, c), _p(cand_cov, c), float(gate), _p(fc, ctypes.c_int32),
-                            _p(out["par"], c), _p(out["cov"], c), _p(out["chi2"], c),
+                            int(bool(joseph)), _p(out["par"], c), _p(out["cov"], c), _p(out["chi2"], c),
                             _p(out["status"], ctypes.c_int32), _p(out["chosen"], ctypes.c_int32),
                             _p(out["cand_chi2"], c), 0 if precision == "f64" else 1, _threads(nthreads))
     if rc != 0:

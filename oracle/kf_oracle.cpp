@@ -547,7 +547,7 @@ void record_batch(int geom, int64_t n, int L, const double* layers, double bz, c
 template <class S>
 void run_track_gated(int geom, V6<S>& p, M6<S>& P, const V3<S>* cand, const M3<S>* ccov, int M,
                      const double* layers, int nl, double b, double gate, const int32_t* forced,
-                     S& chi2, uint32_t& status, int32_t* chosen, double* cand_chi2) {
+                     bool joseph, S& chi2, uint32_t& status, int32_t* chosen, double* cand_chi2) {
   uint32_t flags = 0;
   int done = 0;
   chi2 = S(0.0);
@@ -580,7 +580,7 @@ void run_track_gated(int geom, V6<S>& p, M6<S>& P, const V3<S>* cand, const M3<S
     if (chosen) chosen[k] = best;
     if (best >= 0) {
       S dchi;
-      if (!kalman_update(pt, Pt, cand[size_t(k) * M + best], ccov[size_t(k) * M + best], false, dchi, f)) {
+      if (!kalman_update(pt, Pt, cand[size_t(k) * M + best], ccov[size_t(k) * M + best], joseph, dchi, f)) {
         flags |= f;
         break;
       }
@@ -599,7 +599,7 @@ void run_track_gated(int geom, V6<S>& p, M6<S>& P, const V3<S>* cand, const M3<S
 template <class S>
 void gate_batch(int geom, int64_t n, int L, int M, const double* layers, double bz, const int32_t* nlay,
                 const double* par_in, const double* cov_in, const double* cand_pos, const double* cand_cov,
-                double gate, const int32_t* forced, double* par_out, double* cov_out, double* chi2_out,
+                double gate, const int32_t* forced, int joseph, double* par_out, double* cov_out, double* chi2_out,
                 int32_t* status_out, int32_t* chosen_out, double* cand_chi2_out, int nthreads) {
   const double b = kCLight * bz;
 #ifdef _OPENMP
@@ -633,7 +633,7 @@ void gate_batch(int geom, int64_t n, int L, int M, const double* layers, double 
       S chi2; uint32_t st;
       std::fill(cc.begin(), cc.end(), NAN);
       run_track_gated<S>(geom, p, P, m.data(), V.data(), M, layers, nl, b, gate, forced ? fc.data() : nullptr,
-                         chi2, st, ch.data(), cc.data());
+                         joseph != 0, chi2, st, ch.data(), cc.data());
       const int done = int(st >> 16);
       for (int a = 0; a < 6; ++a) par_out[i * 6 + a] = double(p[a]);
       for (int a = 0; a < 6; ++a) for (int c = 0; c <= a; ++c) cov_out[i * 21 + pk(a, c)] = double(P[a][c]);
@@ -758,18 +758,19 @@ int kfo_filter_record(int geom, int64_t n, int L, const double* layers, double b
 }
 
 // Filter with hit selection among M candidates per layer (see
-// run_track_gated); precision 0 double, 1 float (tolerance sizing only).
+// run_track_gated); the chosen candidate's update in Joseph form if joseph;
+// precision 0 double, 1 float (tolerance sizing only).
 int kfo_gate_run(int geom, int64_t n, int L, int M, const double* layers, double bz, const int32_t* nlay,
                  const double* par_in, const double* cov_in, const double* cand_pos, const double* cand_cov,
-                 double gate, const int32_t* forced, double* par_out, double* cov_out, double* chi2_out,
+                 double gate, const int32_t* forced, int joseph, double* par_out, double* cov_out, double* chi2_out,
                  int32_t* status_out, int32_t* chosen_out, double* cand_chi2_out, int precision, int nthreads) {
   if (n < 0 || L < 0 || M < 1 || (geom != 0 && geom != 1)) return 1;
   if (precision == 0)
     kfo::gate_batch<double>(geom, n, L, M, layers, bz, nlay, par_in, cov_in, cand_pos, cand_cov, gate, forced,
-                            par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
+                            joseph, par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
   else
     kfo::gate_batch<float>(geom, n, L, M, layers, bz, nlay, par_in, cov_in, cand_pos, cand_cov, gate, forced,
-                           par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
+                           joseph, par_out, cov_out, chi2_out, status_out, chosen_out, cand_chi2_out, nthreads);
   return 0;
 }
 

@@ -320,7 +320,8 @@ kf_status_t kf_propagate_gate_update(int32_t geometry, const float* par_in, cons
   if (n_cand < 1 || n_cand > KF_MAX_CANDIDATES || chi2_gate != chi2_gate) return KF_E_SHAPE;
   kf::TrackLayout tl;
   if (!layout_ok(layout, &tl)) return KF_E_LAYOUT;
-  if (flags != 0) return KF_E_FLAGS;
+  if (flags & ~uint32_t(KF_F_PRECISION)) return KF_E_FLAGS;
+  const int prec = (flags & KF_F_JOSEPH) ? 2 : ((flags & KF_F_FP64_INVERSE) ? 1 : 0);
   int block = 256;
   if (tune) {
     block = tune->block_threads;
@@ -353,7 +354,7 @@ kf_status_t kf_propagate_gate_update(int32_t geometry, const float* par_in, cons
   a.b = float(kCLight * double(bz_tesla));
   a.gate = chi2_gate;
   for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
-  const hipError_t e = kf::launch_gate(geometry, block, a, static_cast<hipStream_t>(stream));
+  const hipError_t e = kf::launch_gate(geometry, prec, block, a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
 }
 
@@ -441,13 +442,22 @@ int64_t kf_batched_workspace_size(int64_t n_tracks) {
   return n_tracks < 0 ? 0 : kf::batched_workspace_bytes(n_tracks);
 }
 
-kf_status_t kf_propagate_update_batched(
-    const float* par_in, const float* cov_in, float* par_out, float* cov_out, const float* hit_pos,
-    const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
-    const int32_t* n_layers_per_track,
-    const float* layer_z, const float* layer_r, int32_t max_layers, int64_t n_tracks, float bz_tesla,
-    kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out, void* workspace,
-    int64_t workspace_bytes, const kf_tune_t* tune, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Everything kf_propagate_update_batched checks and sets up except the
+// workspace: the argument checks in the order the header states, the launch
+// shape, and the kernel arguments (the bytes of `a` key the graph cache, so
+// it is cleared first).  Returns KF_OK with *a, *prec, *block filled, or the
+// error; *empty is set when there is nothing to enqueue.
+kf_status_t batched_prepare(const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+                            const float* hit_pos, const float* hit_cov, const int64_t* hit_offset, int64_t n_hits,
+                            const uint8_t* geom, const int32_t* n_layers_per_track, const float* layer_z,
+                            const float* layer_r, int32_t max_layers, int64_t n_tracks, float bz_tesla,
+                            kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out,
+                            const kf_tune_t* tune, kf::BatchedArgs* a, int* prec, int* block_out, bool* empty) {
+  *empty = false;
   if (n_tracks < 0 || n_tracks > KF_BATCHED_MAX_TRACKS || max_layers < 0 || max_layers > KF_MAX_LAYERS ||
       n_hits < 0)
     return KF_E_SHAPE;
@@ -467,44 +477,68 @@ kf_status_t kf_propagate_update_batched(
       return KF_E_FLAGS;
     if (mult == 0) mult = 1;
   }
-  if (n_tracks == 0) return KF_OK;
+  if (n_tracks == 0) {
+    *empty = true;
+    return KF_OK;
+  }
   if (!par_in || !cov_in || !par_out || !cov_out || !geom || !n_layers_per_track || !hit_offset) return KF_E_NULL;
   if (max_layers > 0 && (!hit_pos || !hit_cov || !layer_z || !layer_r)) return KF_E_NULL;
   const void* ptrs[] = {par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, chi2_out, status_out, n_layers_per_track};
   for (const void* p : ptrs)
     if (p && !aligned4(p)) return KF_E_ALIGN;
-  if ((reinterpret_cast<uintptr_t>(hit_offset) & 7u) || (reinterpret_cast<uintptr_t>(workspace) & 7u))
-    return KF_E_ALIGN;
+  if (reinterpret_cast<uintptr_t>(hit_offset) & 7u) return KF_E_ALIGN;
+  memset(a, 0, sizeof(*a));
+  a->par_in = par_in;
+  a->cov_in = cov_in;
+  a->par_out = par_out;
+  a->cov_out = cov_out;
+  a->hit_pos = hit_pos;
+  a->hit_cov = hit_cov;
+  a->hit_offset = hit_offset;
+  a->n_hits = n_hits;
+  a->geom = geom;
+  a->nlay = n_layers_per_track;
+  a->chi2 = chi2_out;
+  a->status = status_out;
+  a->n = n_tracks;
+  a->L = max_layers;
+  a->tpt = tpt;
+  a->schedule = sched;
+  a->waves_mult = mult;
+  a->lay = tl;
+  a->b = float(kCLight * double(bz_tesla));
+  kf::bucket_order(a->order);
+  for (int l = 0; l < max_layers; ++l) {
+    a->layer_z[l] = layer_z[l];
+    a->layer_r[l] = layer_r[l];
+  }
+  *prec = (flags & KF_F_JOSEPH) ? 2 : ((flags & KF_F_FP64_INVERSE) ? 1 : 0);
+  *block_out = block;
+  return KF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kf_status_t kf_propagate_update_batched(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out, const float* hit_pos,
+    const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
+    const int32_t* n_layers_per_track,
+    const float* layer_z, const float* layer_r, int32_t max_layers, int64_t n_tracks, float bz_tesla,
+    kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out, void* workspace,
+    int64_t workspace_bytes, const kf_tune_t* tune, void* stream) {
   kf::BatchedArgs a;
-  memset(&a, 0, sizeof(a));  // the bytes of `a` key the graph cache
+  int prec = 0, block = 0;
+  bool empty = false;
+  const kf_status_t ps = batched_prepare(par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, hit_offset, n_hits, geom,
+                                         n_layers_per_track, layer_z, layer_r, max_layers, n_tracks, bz_tesla, layout,
+                                         flags, chi2_out, status_out, tune, &a, &prec, &block, &empty);
+  if (ps != KF_OK || empty) return ps;
+  if (reinterpret_cast<uintptr_t>(workspace) & 7u) return KF_E_ALIGN;
   if (!kf::batched_carve(workspace, workspace_bytes, n_tracks, &a.ws)) return KF_E_WORKSPACE;
   kf_status_t ds = device_ok();
   if (ds != KF_OK) return ds;
-  a.par_in = par_in;
-  a.cov_in = cov_in;
-  a.par_out = par_out;
-  a.cov_out = cov_out;
-  a.hit_pos = hit_pos;
-  a.hit_cov = hit_cov;
-  a.hit_offset = hit_offset;
-  a.n_hits = n_hits;
-  a.geom = geom;
-  a.nlay = n_layers_per_track;
-  a.chi2 = chi2_out;
-  a.status = status_out;
-  a.n = n_tracks;
-  a.L = max_layers;
-  a.tpt = tpt;
-  a.schedule = sched;
-  a.waves_mult = mult;
-  a.lay = tl;
-  a.b = float(kCLight * double(bz_tesla));
-  kf::bucket_order(a.order);
-  for (int l = 0; l < max_layers; ++l) {
-    a.layer_z[l] = layer_z[l];
-    a.layer_r[l] = layer_r[l];
-  }
-  const int prec = (flags & KF_F_JOSEPH) ? 2 : ((flags & KF_F_FP64_INVERSE) ? 1 : 0);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (flags & KF_F_NO_GRAPH) {
     const hipError_t e = kf::launch_batched(a, prec, block, st);

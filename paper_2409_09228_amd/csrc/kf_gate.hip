@@ -11,7 +11,9 @@
 // plain step); per layer the lane streams its candidates (9 floats each),
 // keeping the best one's hit in registers, then runs the ordinary update
 // with it.  The decision's chi-square is computed with the same expressions
-// as the update's, so the chi-square that decides is the one that is added.
+// (and precision) as the update's, so the chi-square that decides is the one
+// that is added.  The precision flags select the update as in the plain step:
+// FP64 residual-covariance inverse and gain, optionally the Joseph form.
 #include "kf_device.h"
 #include "kf_internal.h"
 #include "kf_lanes.h"
@@ -22,29 +24,33 @@ namespace {
 
 // Chi-square of an update of the prediction (q, Pt) with hit (m, V), and
 // whether the candidate takes part (finite, residual covariance positive
-// definite).  The arithmetic is update_f32's.
+// definite).  R: the arithmetic of the update that follows -- float for the
+// FP32 update (update_f32's expressions), double when S^-1 is taken in FP64
+// (the precision form) -- so the chi-square that decides is the one added.
+template <class R>
 __device__ __forceinline__ bool candidate_chi2(const float q[6], const float Pt[21], const float m[3],
                                                const float V[6], float& chi2) {
-  const float r0 = m[0] - q[0], r1 = m[1] - q[1], r2 = m[2] - q[2];
-  const float S00 = Pt[0] + V[0], S10 = Pt[1] + V[1], S11 = Pt[2] + V[2];
-  const float S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
+  const R r0 = R(m[0] - q[0]), r1 = R(m[1] - q[1]), r2 = R(m[2] - q[2]);
+  const R S00 = R(Pt[0] + V[0]), S10 = R(Pt[1] + V[1]), S11 = R(Pt[2] + V[2]);
+  const R S20 = R(Pt[3] + V[3]), S21 = R(Pt[4] + V[4]), S22 = R(Pt[5] + V[5]);
   const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
-  const float c00 = S11 * S22 - S21 * S21;
-  const float c10 = S20 * S21 - S10 * S22;
-  const float c11 = S00 * S22 - S20 * S20;
-  const float c20 = S10 * S21 - S11 * S20;
-  const float c21 = S10 * S20 - S00 * S21;
-  const float c22 = S00 * S11 - S10 * S10;
-  const float det = S00 * c00 + S10 * c10 + S20 * c20;
-  const bool pd = (S00 > 0.0f) & (c22 > 0.0f) & (det > 0.0f);
-  const float rdet = rcp_t(det);
-  const float i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
-  const float i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
-  const float t0 = i00 * r0 + i10 * r1 + i20 * r2;
-  const float t1 = i10 * r0 + i11 * r1 + i21 * r2;
-  const float t2 = i20 * r0 + i21 * r1 + i22 * r2;
-  chi2 = r0 * t0 + r1 * t1 + r2 * t2;
-  return in_ok & pd & fin(chi2);
+  const R c00 = S11 * S22 - S21 * S21;
+  const R c10 = S20 * S21 - S10 * S22;
+  const R c11 = S00 * S22 - S20 * S20;
+  const R c20 = S10 * S21 - S11 * S20;
+  const R c21 = S10 * S20 - S00 * S21;
+  const R c22 = S00 * S11 - S10 * S10;
+  const R det = S00 * c00 + S10 * c10 + S20 * c20;
+  const bool pd = (S00 > R(0)) & (c22 > R(0)) & (det > R(0));
+  const R rdet = rcp_t(det);
+  const R i00 = c00 * rdet, i10 = c10 * rdet, i11 = c11 * rdet;
+  const R i20 = c20 * rdet, i21 = c21 * rdet, i22 = c22 * rdet;
+  const R t0 = i00 * r0 + i10 * r1 + i20 * r2;
+  const R t1 = i10 * r0 + i11 * r1 + i21 * r2;
+  const R t2 = i20 * r0 + i21 * r1 + i22 * r2;
+  const R c = r0 * t0 + r1 * t1 + r2 * t2;
+  chi2 = float(c);
+  return in_ok & pd & fin(c) & fin(chi2);
 }
 
 // STREAM: every track runs all layers (no per-track counts), so every wave
@@ -98,7 +104,7 @@ struct Candidates {
 
 // One layer: propagate, select, update.  Returns status bits; on success
 // (p, C, d) hold the new state and `best` the candidate used (-1: a hole).
-template <int GEOM, bool ZIN, int KIND, bool WIDE, bool STREAM>
+template <int GEOM, bool ZIN, int PREC, int KIND, bool WIDE, bool STREAM>
 __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STREAM>& cands, int k, float p[6], float C[21],
                                                DirT<float>& d, float& chi2, int& best) {
   float q[6], Pt[21];
@@ -117,7 +123,8 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STRE
   for (int j = 0; j < cands.a.M; ++j) {
     float m[3], V[6], c;
     cands.load(k, j, m, V);
-    const bool take = candidate_chi2(q, Pt, m, V, c) & (c <= cands.a.gate) & (c < bchi);
+    const bool ok = PREC == PREC_F32 ? candidate_chi2<float>(q, Pt, m, V, c) : candidate_chi2<double>(q, Pt, m, V, c);
+    const bool take = ok & (c <= cands.a.gate) & (c < bchi);
     best = take ? j : best;
     bchi = take ? c : bchi;
 #pragma unroll
@@ -128,7 +135,7 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STRE
   if (best >= 0) {
     const float phi = q[4], theta = q[5];
     float dchi;
-    const uint32_t fu = update<GEOM, PREC_F32, float>(q, Pt, mb, Vb, dchi);
+    const uint32_t fu = update<GEOM, PREC, float>(q, Pt, mb, Vb, dchi);
     if (fu) return fu;
     rotate_by(dq.sp, dq.cp, q[4] - phi, q[4]);
     rotate_by(dq.st, dq.ct, q[5] - theta, q[5]);
@@ -144,7 +151,7 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STRE
 
 }  // namespace
 
-template <int GEOM, int KIND, bool WIDE, bool STREAM>
+template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM>
 __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
@@ -166,8 +173,8 @@ __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
   dir_init(p, d);
   for (int k = 0; k < nl && !flags; ++k) {
     int best = -1;
-    const uint32_t f = (GEOM == 0 && k > 0) ? gate_layer<GEOM, true>(cands, k, p, C, d, chi2, best)
-                                            : gate_layer<GEOM, false>(cands, k, p, C, d, chi2, best);
+    const uint32_t f = (GEOM == 0 && k > 0) ? gate_layer<GEOM, true, PREC>(cands, k, p, C, d, chi2, best)
+                                            : gate_layer<GEOM, false, PREC>(cands, k, p, C, d, chi2, best);
     if (f) {
       flags = f;
       break;
@@ -181,28 +188,35 @@ __global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
   if (a.status) a.status[i] = int32_t(flags | (uint32_t(done) << 16));
 }
 
-template <int GEOM, bool WIDE>
+template <int GEOM, int PREC, bool WIDE>
 static hipError_t launch_kind(int block, const GateArgs& a, hipStream_t s) {
   const dim3 grid(unsigned((a.n + block - 1) / block));
   const bool stream = a.nlay == nullptr;
   if (a.lay.kind == KF_AOS)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOS, WIDE, false>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, PREC, KF_AOS, WIDE, false>), grid, dim3(block), 0, s, a);
   else if (a.lay.kind == KF_AOSOA && stream)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE, true>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, PREC, KF_AOSOA, WIDE, true>), grid, dim3(block), 0, s, a);
   else if (a.lay.kind == KF_AOSOA)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_AOSOA, WIDE, false>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, PREC, KF_AOSOA, WIDE, false>), grid, dim3(block), 0, s, a);
   else if (stream)
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE, true>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, PREC, KF_SOA, WIDE, true>), grid, dim3(block), 0, s, a);
   else
-    hipLaunchKernelGGL((kf_gate_kernel<GEOM, KF_SOA, WIDE, false>), grid, dim3(block), 0, s, a);
+    hipLaunchKernelGGL((kf_gate_kernel<GEOM, PREC, KF_SOA, WIDE, false>), grid, dim3(block), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_gate(int geom, int block, const GateArgs& a, hipStream_t s) {
+template <int PREC>
+static hipError_t launch_prec(int geom, bool wide, int block, const GateArgs& a, hipStream_t s) {
+  if (geom == 0) return wide ? launch_kind<0, PREC, true>(block, a, s) : launch_kind<0, PREC, false>(block, a, s);
+  return wide ? launch_kind<1, PREC, true>(block, a, s) : launch_kind<1, PREC, false>(block, a, s);
+}
+
+hipError_t launch_gate(int geom, int prec, int block, const GateArgs& a, hipStream_t s) {
   // 64-bit addressing once any array reaches 4 GiB (the candidates' covariances are the largest)
   const bool wide = layout_floats(a.n, 6 * a.M, a.L, a.lay) * 4 >= (int64_t(1) << 32) || needs_wide(a.n, a.L, a.lay);
-  if (geom == 0) return wide ? launch_kind<0, true>(block, a, s) : launch_kind<0, false>(block, a, s);
-  return wide ? launch_kind<1, true>(block, a, s) : launch_kind<1, false>(block, a, s);
+  if (prec == PREC_F32) return launch_prec<PREC_F32>(geom, wide, block, a, s);
+  if (prec == PREC_F64) return launch_prec<PREC_F64>(geom, wide, block, a, s);
+  return launch_prec<PREC_F64_JOSEPH>(geom, wide, block, a, s);
 }
 
 }  // namespace kf

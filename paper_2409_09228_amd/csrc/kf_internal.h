@@ -99,7 +99,7 @@ struct GateArgs {
   float layer[KF_MAX_LAYERS];
 };
 
-hipError_t launch_gate(int geom, int block, const GateArgs& a, hipStream_t s);
+hipError_t launch_gate(int geom, int prec, int block, const GateArgs& a, hipStream_t s);
 
 // precision variant: 0 FP32, 1 FP64 gain + plain covariance, 2 FP64 gain + Joseph
 hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a, hipStream_t s);

@@ -675,7 +675,7 @@ class GateLauncher:
     """A kf_propagate_gate_update call on a staged sample and its staged
     candidates, every argument converted once; outputs allocated here."""
 
-    def __init__(self, st: dict, cands: dict, gate: float, tune=None, stream=None, chosen=True):
+    def __init__(self, st: dict, cands: dict, gate: float, tune=None, stream=None, chosen=True, flags: int = 0):
         import torch
         _require_cuda(st["par"], st["cov"], cands["cand_pos"], cands["cand_cov"], st["nlay"])
         dev = st["par"].device
@@ -692,7 +692,7 @@ class GateLauncher:
         self._args = (int(st["geom"]), _ptr(st["par"]), _ptr(st["cov"]), _ptr(self.par_out), _ptr(self.cov_out),
                       _ptr(cands["cand_pos"]), _ptr(cands["cand_cov"]), int(cands["M"]), float(gate),
                       self._layers.ctypes.data_as(ctypes.c_void_p), int(self._layers.shape[0]), _ptr(st["nlay"]),
-                      int(n), float(st["bz"]), Layout(*st["layout"]), 0, _ptr(self.chi2), _ptr(self.status),
+                      int(n), float(st["bz"]), Layout(*st["layout"]), int(flags), _ptr(self.chi2), _ptr(self.status),
                       _ptr(self.chosen), None if self._tune is None else ctypes.byref(self._tune), sp)
 
     def __call__(self):

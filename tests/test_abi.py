@@ -162,7 +162,8 @@ def test_gate_validation_before_any_device_call():
     assert call(M=65) == 2
     assert call(gate=float("nan")) == 2
     assert call(layout=(1, 12)) == 3
-    assert call(flags=1) == 8
+    assert call(flags=4) == 8          # only the precision bits
+    assert call(flags=256) == 8
     assert call(tune=(512, 1)) == 8
     assert call(par=None) == 1
     assert call(cand=None) == 1

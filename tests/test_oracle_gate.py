@@ -42,6 +42,27 @@ def test_one_candidate_no_gate_is_the_one_hit_filter(samples, name):
     assert np.all(r["chosen"][_valid(r)] == 0)
 
 
+@pytest.mark.parametrize("name", ["z", "r"])
+def test_joseph_selection(samples, name):
+    """The Joseph form of the selected update: with one candidate and no gate
+    it is the Joseph one-hit filter bit for bit; with candidates and a gate
+    (the same choices forced) it equals the plain form to FP64 rounding."""
+    s = samples[name]
+    r = O.gate_sample(s, S.multi_hit(s, 1), np.inf, joseph=True)
+    one = O.run_sample(s, joseph=True)
+    for a, b in zip((r["par"], r["cov"], r["chi2"], r["status"]), one):
+        np.testing.assert_array_equal(a, b)
+    mh = S.multi_hit(s, 8, spread=10.0)
+    plain = O.gate_sample(s, mh, 30.0)
+    L = plain["chosen"].shape[0]
+    forced = np.where(_valid(plain), plain["chosen"], -1)
+    jos = O.gate_sample(s, mh, 30.0, forced=forced, joseph=True)
+    np.testing.assert_array_equal(jos["status"], plain["status"])
+    np.testing.assert_allclose(jos["par"], plain["par"], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(jos["chi2"], plain["chi2"], rtol=1e-9, atol=1e-11)
+    assert L == s["hit_pos"].shape[0]
+
+
 @pytest.mark.parametrize("name,dof,median", [("z", 3, 2.36597), ("r", 2, 1.38629)])
 def test_chi2_of_the_tracks_own_hit_follows_the_chi2_law(samples, name, dof, median):
     s = samples[name]
