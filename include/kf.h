@@ -360,6 +360,33 @@ kf_status_t kf_propagate_update_batched(
 void kf_batched_release(void);
 
 /*
+ * kf_propagate_update_batched_noalloc -- kf_propagate_update_batched for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  It computes exactly what
+ * kf_propagate_update_batched computes (the same kernels, bit for bit) but
+ * takes no workspace: its planning workspace is a fixed device array inside
+ * the library, about 4 MiB per GPU, sized for KF_NOALLOC_MAX_TRACKS tracks and
+ * held by each GPU the library runs on until the process ends.  It calls no
+ * allocating routine: no hipMalloc, no graph is built (the four kernels are
+ * enqueued on `stream` directly, so a caller capturing that stream records
+ * them in its own graph).  KF_F_NO_GRAPH is accepted and changes nothing.
+ *
+ * Arguments as kf_propagate_update_batched without workspace and
+ * workspace_bytes.  n_tracks above KF_NOALLOC_MAX_TRACKS: KF_E_WORKSPACE,
+ * nothing enqueued.  Every call on one GPU shares that GPU's array, and the
+ * planning kernels clear what must start at zero on every call: calls that
+ * overlap in time on one GPU (different streams, or different host threads)
+ * race and must be serialised by the caller.
+ */
+#define KF_NOALLOC_MAX_TRACKS ((int64_t)1 << 20)
+kf_status_t kf_propagate_update_batched_noalloc(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out,
+    const float* hit_pos, const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
+    const int32_t* n_layers_per_track, const float* layer_z, const float* layer_r, int32_t max_layers,
+    int64_t n_tracks, float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out,
+    int32_t* status_out, const kf_tune_t* tune, void* stream);
+
+/*
  * kf_propagate_update_z_f64 / kf_propagate_update_r_f64 -- the same steps in
  * FP64 end to end: double arrays (same layouts, 8-byte elements, 8-byte
  * aligned), field constant and layer table in double, all arithmetic in

@@ -549,6 +549,34 @@ kf_status_t kf_propagate_update_batched(
   return batched_via_graph(a, prec, block, dev, st);
 }
 
+kf_status_t kf_propagate_update_batched_noalloc(
+    const float* par_in, const float* cov_in, float* par_out, float* cov_out, const float* hit_pos,
+    const float* hit_cov, const int64_t* hit_offset, int64_t n_hits, const uint8_t* geom,
+    const int32_t* n_layers_per_track, const float* layer_z, const float* layer_r, int32_t max_layers,
+    int64_t n_tracks, float bz_tesla, kf_layout_t layout, uint32_t flags, float* chi2_out, int32_t* status_out,
+    const kf_tune_t* tune, void* stream) {
+  kf::BatchedArgs a;
+  int prec = 0, block = 0;
+  bool empty = false;
+  const kf_status_t ps = batched_prepare(par_in, cov_in, par_out, cov_out, hit_pos, hit_cov, hit_offset, n_hits, geom,
+                                         n_layers_per_track, layer_z, layer_r, max_layers, n_tracks, bz_tesla, layout,
+                                         flags, chi2_out, status_out, tune, &a, &prec, &block, &empty);
+  if (ps != KF_OK || empty) return ps;
+  if (n_tracks > KF_NOALLOC_MAX_TRACKS) return KF_E_WORKSPACE;
+  kf_status_t ds = device_ok();
+  if (ds != KF_OK) return ds;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KF_E_DEVICE;
+  void* scratch = nullptr;
+  int64_t scratch_bytes = 0;
+  if (kf::noalloc_scratch(dev, &scratch, &scratch_bytes) != hipSuccess) return KF_E_DEVICE;
+  if (!kf::batched_carve(scratch, scratch_bytes, n_tracks, &a.ws)) return KF_E_WORKSPACE;
+  // enqueued directly: no graph is built (that would allocate); a caller
+  // capturing this stream gets the four kernels as nodes of its own graph
+  const hipError_t e = kf::launch_batched(a, prec, block, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
 void kf_batched_release(void) {
   GraphCache& gc = graphs();
   std::lock_guard<std::mutex> g(gc.mu);

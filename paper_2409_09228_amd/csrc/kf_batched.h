@@ -53,5 +53,9 @@ bool batched_carve(void* ws, int64_t bytes, int64_t n, BatchedWorkspace* out);
 void bucket_order(int32_t order[KF_NBUCKETS]);
 // Enqueue the three planning kernels and the persistent run.
 hipError_t launch_batched(const BatchedArgs& a, int prec, int block, hipStream_t s);
+// Device address and size of the fixed planning workspace of
+// kf_propagate_update_batched_noalloc on device `dev` (the current device):
+// looked up once per device, then kept.
+hipError_t noalloc_scratch(int dev, void** ptr, int64_t* bytes);
 
 }  // namespace kf

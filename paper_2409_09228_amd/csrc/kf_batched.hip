@@ -17,6 +17,8 @@
 // A work item's tracks are gathered by index: their state through the track
 // layout, their hits from ragged per-track runs.
 #include "kf_batched.h"
+
+#include <mutex>
 #include "kf_lanes.h"
 #include "kf_track.h"
 
@@ -417,6 +419,32 @@ static int64_t max_slots(int64_t n) { return n + int64_t(KF_NBUCKETS + 1) * 128;
 
 int64_t batched_workspace_bytes(int64_t n) {
   return align256(4 * (4 * KF_NBUCKETS + 5)) + align256(4 * max_slots(n));
+}
+
+// The planning workspace of kf_propagate_update_batched_noalloc: a fixed
+// device array, one per device, sized for KF_NOALLOC_MAX_TRACKS tracks
+// (about 4 MiB), held until the process ends.  In host code its name is a
+// host-side stand-in, not a device address: host code uses only the
+// address that hipGetSymbolAddress returns for the current device.
+constexpr int64_t kScratchBytes = (((4 * (4 * KF_NBUCKETS + 5)) + 255) & ~int64_t(255)) +
+                                  ((4 * (KF_NOALLOC_MAX_TRACKS + int64_t(KF_NBUCKETS + 1) * 128) + 255) & ~int64_t(255));
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+hipError_t noalloc_scratch(int dev, void** ptr, int64_t* bytes) {
+  static std::mutex mu;
+  static void* addr[64];
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kScratchBytes;
+  return hipSuccess;
 }
 
 bool batched_carve(void* ws, int64_t bytes, int64_t n, BatchedWorkspace* out) {

@@ -118,6 +118,10 @@ def lib():
                                                   ctypes.c_uint32, vp, vp, vp, i64, ctypes.POINTER(Tune), vp]
         L.kf_propagate_update_batched.restype = ctypes.c_int
         L.kf_batched_release.restype = None
+        L.kf_propagate_update_batched_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, vp, vp, vp, i32,
+                                                          i64, f32, Layout, ctypes.c_uint32, vp, vp,
+                                                          ctypes.POINTER(Tune), vp]
+        L.kf_propagate_update_batched_noalloc.restype = ctypes.c_int
         L.kf_array_floats.argtypes = [i32, i32, i64, Layout]
         L.kf_array_floats.restype = ctypes.c_int64
         L.kf_status_string.argtypes = [ctypes.c_int]
@@ -592,6 +596,34 @@ def run_batched(st: dict, flags: int = 0, tune=None, stream=None, workspace=None
     BatchedLauncher(st, (par_out, cov_out), chi2, status, flags=flags, tune=tune, stream=stream,
                     workspace=workspace)()
     return par_out, cov_out, chi2, status
+
+
+NOALLOC_MAX_TRACKS = 1 << 20
+
+
+def run_batched_noalloc(st: dict, out=None, flags: int = 0, tune=None, stream=None):
+    """kf_propagate_update_batched_noalloc on a staged mixed sample: no
+    workspace (the library's fixed device array), no graph.  `out` =
+    (par_out, cov_out, chi2, status), allocated here if None.  Calls that
+    overlap on one GPU race (they share that array)."""
+    import torch
+    dev = st["par"].device
+    if out is None:
+        out = (torch.empty_like(st["par"]), torch.empty_like(st["cov"]),
+               torch.empty(st["n"], dtype=torch.float32, device=dev),
+               torch.empty(st["n"], dtype=torch.int32, device=dev))
+    _require_cuda(st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["hit_offset"], st["geom"], st["nlay"], *out)
+    lz = np.ascontiguousarray(st["layer_z"], np.float32)
+    lr = np.ascontiguousarray(st["layer_r"], np.float32)
+    tn = None if tune is None else ctypes.byref(make_tune(tune))
+    with torch.cuda.device(dev):
+        rc = lib().kf_propagate_update_batched_noalloc(
+            _ptr(st["par"]), _ptr(st["cov"]), _ptr(out[0]), _ptr(out[1]), _ptr(st["hit_pos"]), _ptr(st["hit_cov"]),
+            _ptr(st["hit_offset"]), int(st["hit_pos"].shape[0]), _ptr(st["geom"]), _ptr(st["nlay"]),
+            lz.ctypes.data_as(ctypes.c_void_p), lr.ctypes.data_as(ctypes.c_void_p), int(st["L"]), int(st["n"]),
+            float(st["bz"]), Layout(*st["layout"]), int(flags), _ptr(out[2]), _ptr(out[3]), tn, _stream(stream))
+    _check(rc, "kf_propagate_update_batched_noalloc")
+    return out
 
 
 def release_graphs():
