@@ -506,35 +506,36 @@ def bench_batched(args, sample):
 
 
 def bench_adjoint(args, sample):
-    """Forward + hand-written backward of sum chi2 (planes): checkpoints of
-    every layer, of every 2nd/4th/8th layer (recomputing inside a segment),
-    and recomputation from the seed."""
+    """Forward + hand-written backward of sum chi2 (planes or cylinders, the
+    sample's geometry): checkpoints of every layer, of every 2nd/4th/8th
+    layer (recomputing inside a segment), and recomputation from the seed."""
     import torch
     from paper_2409_09228_amd import kf as K
     stream = torch.cuda.current_stream()
     layout = parse_layout(args.layout)
     st = K.stage_sample(sample, layout)
+    geom = int(st["geom"])
     n, L = st["n"], st["L"]
     updates = int(sample["nlay"].sum())
     outs = (torch.empty_like(st["par"]), torch.empty_like(st["cov"]))
     chi2 = torch.empty(n, device="cuda")
     status = torch.empty(n, dtype=torch.int32, device="cuda")
     w = torch.ones(n, device="cuda")
-    fwd = K.StepLauncher(0, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
+    fwd = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
                          out=outs, chi2=chi2, status=status, nlay=st["nlay"], layout=layout, stream=stream)
     steps = max(3, args.steps // 4)
     ms = {"forward_plain": time_launches(fwd, steps, stream)}
     totals, ck_bytes = {}, {}
     for every in (1, 2, 4, 8):
         ck = K.checkpoint_buffer(n, L, layout, every=every)
-        fwd_ck = K.StepLauncher(0, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
+        fwd_ck = K.StepLauncher(geom, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"], st["bz"], n,
                                 out=outs, chi2=chi2, status=status, nlay=st["nlay"], layout=layout, ckpt=ck,
                                 ckpt_every=every, stream=stream)
         fwd_ck()
         torch.cuda.synchronize()
 
         def bwd_ck(ck=ck, every=every):
-            K.chi2_backward_z(st, status, w, ckpt=ck, ckpt_every=every, stream=stream)
+            K.chi2_backward(st, status, w, ckpt=ck, ckpt_every=every, stream=stream)
 
         ms[f"forward_checkpoint_every{every}"] = time_launches(fwd_ck, steps, stream)
         ms[f"backward_checkpoint_every{every}"] = time_launches(bwd_ck, steps, stream)
@@ -543,7 +544,7 @@ def bench_adjoint(args, sample):
         del ck, fwd_ck
 
     def bwd_re():
-        K.chi2_backward_z(st, status, w, ckpt=None, stream=stream)
+        K.chi2_backward(st, status, w, ckpt=None, stream=stream)
 
     ms["backward_recompute"] = time_launches(bwd_re, max(2, steps // 4), stream)
     totals["recompute"] = ms["forward_plain"] + ms["backward_recompute"]
@@ -553,14 +554,16 @@ def bench_adjoint(args, sample):
     # read (checkpoint slots, or the seed; hits; status; dL/dchi2) and write
     # (dL/dm per layer, dL/dp0) once
     every = int(best[len("checkpoint_every"):]) if best.startswith("checkpoint_every") else 0
-    n_slots = -(-L // every) if every else 0
-    bwd_bytes = (n * (n_slots * 27 * 4 + (0 if every else 27 * 4) + 4 + 4 + 6 * 4)
+    # checkpoint slots of the layers each track applied: ceil(n_i / every)
+    nl = np.asarray(sample["nlay"], np.int64)
+    slots = int((-(-nl // every)).sum()) if every else 0
+    bwd_bytes = (slots * 27 * 4 + n * ((0 if every else 27 * 4) + 4 + 4 + 6 * 4)
                  + updates * (LAYER_BYTES + 3 * 4))
     bwd_ms = ms[f"backward_checkpoint_every{every}" if every else "backward_recompute"]
     bwd_gbs = bwd_bytes / (bwd_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(bwd_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(bwd_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "kf_adjoint_z_kernel", "hbm_algorithmic_bytes_per_launch": int(bwd_bytes),
+                "kernel": "kf_adjoint_kernel<%d>" % geom, "hbm_algorithmic_bytes_per_launch": int(bwd_bytes),
                 "valu_frac_charged": None,
                 "note": "the backward's flops have no algorithmic count; HBM fraction only"}
     return {

@@ -279,15 +279,23 @@ kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out,
                       float bz_tesla, kf_layout_t layout, float* smoothed, const kf_tune_t* tune, void* stream);
 
 /*
- * kf_chi2_backward_z -- adjoint of L = sum_i grad_chi2[i] * chi2_i for the plane
- * filter (kf_propagate_update_z in FP32, flags 0): dL/d(hit positions),
+ * kf_chi2_backward -- adjoint of L = sum_i grad_chi2[i] * chi2_i for the
+ * filter through planes (geometry 0, kf_propagate_update_z) or cylinders
+ * (geometry 1, kf_propagate_update_r), FP32, flags 0: dL/d(hit positions),
  * dL/d(seed parameters) and, optionally, dL/d(seed covariance).  chi2_i sums
  * r^T S^-1 r over the layers track i applied (the paper's step, Sec. 3.2;
  * the chi-square itself is this project's addition).  The derivative is the
  * full one, including the covariance's dependence on the parameters through
- * the Jacobian (whose own derivative is taken by dual numbers).
+ * the Jacobian (whose own derivative is taken by dual numbers).  On
+ * cylinders the path length to the crossing depends on the parameters
+ * implicitly (Sec. 3.2: the barrel propagation is an iteration); its
+ * derivative is the implicit-function one at the iteration's result,
+ * -g_p / g_s of g = x(s)^2 + y(s)^2 - r^2, which is also what the forward's
+ * Jacobian uses.
  *
+ *   geometry       0 planes, 1 cylinders (else KF_E_SHAPE)
  *   par_in .. n_tracks, bz_tesla, layout   the forward call's inputs
+ *                  (layers: layer_z or layer_r, HOST)
  *   status_fwd     [n_tracks] the forward's status words: track i's
  *                  gradient runs over its first (status >> 16) layers
  *   ckpt           the forward's ckpt_out, or NULL to recompute the entering
@@ -303,12 +311,18 @@ kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out,
  *   grad_par_in    [6] per track in `layout`
  *   grad_cov_in    [21] per track in `layout`, or NULL
  */
+kf_status_t kf_chi2_backward(
+    int32_t geometry, const float* par_in, const float* cov_in, const float* hit_pos, const float* hit_cov,
+    const float* layers, int32_t n_layers, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
+    const int32_t* status_fwd, const float* ckpt, int32_t ckpt_every, const float* grad_chi2,
+    float* grad_hit_pos, float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream);
+/* kf_chi2_backward_z -- kf_chi2_backward with geometry 0 (planes). */
 kf_status_t kf_chi2_backward_z(
     const float* par_in, const float* cov_in, const float* hit_pos, const float* hit_cov,
     const float* layer_z, int32_t n_layers, int64_t n_tracks, float bz_tesla, kf_layout_t layout,
     const int32_t* status_fwd, const float* ckpt, int32_t ckpt_every, const float* grad_chi2,
     float* grad_hit_pos, float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream);
-/* Floats of a checkpoint buffer for kf_propagate_update_z / kf_chi2_backward_z:
+/* Floats of a checkpoint buffer for kf_propagate_update_z / _r and kf_chi2_backward:
  * ceil(n_layers / ckpt_every) per-layer slots of 27 floats per track in
  * `layout`; 0 for invalid arguments. */
 int64_t kf_checkpoint_floats(int64_t n_tracks, int32_t n_layers, int32_t ckpt_every, kf_layout_t layout);

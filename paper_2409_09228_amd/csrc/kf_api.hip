@@ -229,11 +229,12 @@ kf_status_t batched_via_graph(const kf::BatchedArgs& a, int prec, int block, int
 
 extern "C" {
 
-kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const float* hit_pos,
-                               const float* hit_cov, const float* layer_z, int32_t n_layers, int64_t n_tracks,
-                               float bz_tesla, kf_layout_t layout, const int32_t* status_fwd, const float* ckpt,
-                               int32_t ckpt_every, const float* grad_chi2, float* grad_hit_pos,
-                               float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream) {
+kf_status_t kf_chi2_backward(int32_t geometry, const float* par_in, const float* cov_in, const float* hit_pos,
+                             const float* hit_cov, const float* layers, int32_t n_layers, int64_t n_tracks,
+                             float bz_tesla, kf_layout_t layout, const int32_t* status_fwd, const float* ckpt,
+                             int32_t ckpt_every, const float* grad_chi2, float* grad_hit_pos, float* grad_par_in,
+                             float* grad_cov_in, const kf_tune_t* tune, void* stream) {
+  if (geometry != 0 && geometry != 1) return KF_E_SHAPE;
   if (n_tracks < 0 || n_layers < 0 || n_layers > KF_MAX_LAYERS) return KF_E_SHAPE;
   const int ck_shift = ckpt_shift(ckpt_every);
   if (ckpt && ck_shift < 0) return KF_E_SHAPE;
@@ -246,7 +247,7 @@ kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const f
   }
   if (n_tracks == 0) return KF_OK;
   if (!par_in || !cov_in || !status_fwd || !grad_chi2 || !grad_par_in) return KF_E_NULL;
-  if (n_layers > 0 && (!hit_pos || !hit_cov || !layer_z || !grad_hit_pos)) return KF_E_NULL;
+  if (n_layers > 0 && (!hit_pos || !hit_cov || !layers || !grad_hit_pos)) return KF_E_NULL;
   const void* ptrs[] = {par_in, cov_in, hit_pos, hit_cov, status_fwd, ckpt, grad_chi2, grad_hit_pos, grad_par_in,
                         grad_cov_in};
   for (const void* p : ptrs)
@@ -270,9 +271,19 @@ kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const f
   a.Lck = ckpt ? (n_layers + (1 << ck_shift) - 1) >> ck_shift : n_layers;
   a.lay = tl;
   a.b = float(kCLight * double(bz_tesla));
-  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layer_z[l] : 0.0f;
-  const hipError_t e = kf::launch_adjoint_z(block, a, static_cast<hipStream_t>(stream));
+  for (int l = 0; l < KF_MAX_LAYERS; ++l) a.layer[l] = l < n_layers ? layers[l] : 0.0f;
+  const hipError_t e = kf::launch_adjoint(geometry, block, a, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? KF_OK : KF_E_LAUNCH;
+}
+
+kf_status_t kf_chi2_backward_z(const float* par_in, const float* cov_in, const float* hit_pos,
+                               const float* hit_cov, const float* layer_z, int32_t n_layers, int64_t n_tracks,
+                               float bz_tesla, kf_layout_t layout, const int32_t* status_fwd, const float* ckpt,
+                               int32_t ckpt_every, const float* grad_chi2, float* grad_hit_pos,
+                               float* grad_par_in, float* grad_cov_in, const kf_tune_t* tune, void* stream) {
+  return kf_chi2_backward(0, par_in, cov_in, hit_pos, hit_cov, layer_z, n_layers, n_tracks, bz_tesla, layout,
+                          status_fwd, ckpt, ckpt_every, grad_chi2, grad_hit_pos, grad_par_in, grad_cov_in, tune,
+                          stream);
 }
 
 kf_status_t kf_smooth(int32_t geometry, const float* ckpt, const float* par_out, const float* cov_out,

@@ -164,6 +164,8 @@ __device__ __forceinline__ void helix_sinc_t(float u, float& su, float& cu, floa
 __device__ __forceinline__ float sqrt_t(float x) { return sqrtf(x); }
 __device__ __forceinline__ float fmax_t(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ float fabs_t(float x) { return fabsf(x); }
+__device__ __forceinline__ float val(float x) { return x; }
+__device__ __forceinline__ double val(double x) { return x; }
 
 // The same helpers in FP64 (the full-FP64 form of the step).  sin and cos are
 // the library's; the division is exact IEEE division.  sinc u and G(u) use
@@ -366,20 +368,16 @@ struct CylJac {
   T x0, x1, x3, x4, y0, y1, y3, y4, z0, z1, z3, z4, z5, f0, f1, f3, f4;
 };
 
-// The crossing q and its Jacobian J; returns the status bits.  d: sin and
-// cos of the direction angles of p on entry, of q on return.  inc (if not
-// NULL): the increments q - p of x, y, z and phi at full precision (entries
-// 0, 1, 2, 4).
+// The search: closed-form reachability, then the path length s from the
+// straight-line start and five Newton steps.  sp, cp: sin and cos of phi.
 template <class T>
-__device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, T rk, T b, T q[6], CylJac<T>& J,
-                                                      T* inc = nullptr) {
-  const T sth = d.st, cth = d.ct, sp = d.sp, cp = d.cp;
+__device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T& cp, T rk, T b, bool& reachable) {
   const T om = -b * p[3];
   const T x = p[0], y = p[1];
   const T rho2 = x * x + y * y;
   const T rk2 = rk * rk;
   const T reach = 0.5f * om * (rk2 - rho2) + (x * sp - y * cp);
-  const bool reachable = fabs_t(reach) <= rk;
+  reachable = fabs_t(reach) <= rk;
   const T beta = x * cp + y * sp;
   T s = -beta + sqrt_t(fmax_t(beta * beta - rho2 + rk2, T(0)));
 #pragma unroll
@@ -398,6 +396,22 @@ __device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, 
     const T gp = 2.0f * (X * cP + Y * sP);
     s = s - gg * rcp_t(gp);
   }
+  return s;
+}
+
+// The state after transverse path s (the search's result) and the Jacobian
+// F there, the path length's dependence on p taken from the implicit
+// function x(s)^2 + y(s)^2 = rk^2.  sth, cth, sp, cp: sin and cos of theta
+// and phi of p; sP, cP: of phi at the crossing.  Returns whether the point
+// lies on the cylinder (|x^2 + y^2 - rk^2| <= 2e-4 rk^2).  T: float, or dual
+// numbers (then s carries ds/dp); S: the geometry's scalar.
+template <class T, class S>
+__device__ __forceinline__ bool cylinder_at(const T p[6], const T& sth, const T& cth, const T& sp, const T& cp,
+                                            const T& s, S rk, S b, T q[6], CylJac<T>& J, T& sP, T& cP,
+                                            T* inc = nullptr) {
+  const T om = -b * p[3];
+  const T x = p[0], y = p[1];
+  const S rk2 = rk * rk;
   const T u = 0.5f * om * s;
   T su, cu, sinc, g;
   helix_trig_t(u, su, cu, sinc, g);
@@ -406,11 +420,9 @@ __device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, 
   const T ch = s * sinc;
   const T dx = ch * cA, dy = ch * sA;
   const T X = x + dx, Y = y + dy;
-  const T cP = cA * cu - sA * su;
-  const T sP = sA * cu + cA * su;
-  d.cp = cP;
-  d.sp = sP;
-  const bool on_surface = fabs_t(X * X + Y * Y - rk2) <= T(2.0e-4f) * rk2;
+  cP = cA * cu - sA * su;
+  sP = sA * cu + cA * su;
+  const bool on_surface = fabs_t(val(X * X + Y * Y - rk2)) <= decltype(val(rk2))(2.0e-4f) * val(rk2);
   const T rsth = rcp_t(sth);
   const T cot = cth * rsth;
   q[0] = X;
@@ -440,6 +452,22 @@ __device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, 
   J.y0 = sP * dsx, J.y1 = 1.0f + sP * dsy, J.y3 = Jyk + sP * dsk, J.y4 = Jyf + sP * dsf;
   J.z0 = cot * dsx, J.z1 = cot * dsy, J.z3 = cot * dsk, J.z4 = cot * dsf, J.z5 = Jzt;
   J.f0 = om * dsx, J.f1 = om * dsy, J.f3 = Jfk + om * dsk, J.f4 = 1.0f + om * dsf;
+  return on_surface;
+}
+
+// The crossing q and its Jacobian J; returns the status bits.  d: sin and
+// cos of the direction angles of p on entry, of q on return.  inc (if not
+// NULL): the increments q - p of x, y, z and phi at full precision (entries
+// 0, 1, 2, 4).
+template <class T>
+__device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, T rk, T b, T q[6], CylJac<T>& J,
+                                                      T* inc = nullptr) {
+  bool reachable;
+  const T s = cylinder_search(p, d.sp, d.cp, rk, b, reachable);
+  T sP, cP;
+  const bool on_surface = cylinder_at<T, T>(p, d.st, d.ct, d.sp, d.cp, s, rk, b, q, J, sP, cP, inc);
+  d.cp = cP;
+  d.sp = sP;
   return !reachable ? S_NO_CROSSING : (!on_surface ? S_NEWTON : 0u);
 }
 

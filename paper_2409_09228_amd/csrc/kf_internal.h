@@ -60,7 +60,7 @@ struct AdjointArgs {
   float layer[KF_MAX_LAYERS];
 };
 
-hipError_t launch_adjoint_z(int block, const AdjointArgs& a, hipStream_t s);
+hipError_t launch_adjoint(int geom, int block, const AdjointArgs& a, hipStream_t s);
 
 // Smoother over the layers the filter applied (kf_smooth.hip).
 struct SmoothArgs {

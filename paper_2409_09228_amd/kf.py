@@ -94,6 +94,8 @@ def lib():
         L.kf_chi2_backward_z.argtypes = [vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, vp, i32, vp, vp, vp, vp,
                                          ctypes.POINTER(Tune), vp]
         L.kf_chi2_backward_z.restype = ctypes.c_int
+        L.kf_chi2_backward.argtypes = [i32] + L.kf_chi2_backward_z.argtypes
+        L.kf_chi2_backward.restype = ctypes.c_int
         L.kf_checkpoint_floats.argtypes = [i64, i32, i32, Layout]
         L.kf_smooth.argtypes = [i32, vp, vp, vp, vp, vp, i32, i64, f32, Layout, vp, ctypes.POINTER(Tune), vp]
         L.kf_smooth.restype = ctypes.c_int
@@ -733,12 +735,35 @@ class GateLauncher:
             raise KFError(rc, "kf_propagate_gate_update")
 
 
-def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,
-                    ckpt_every: int = 1):
-    """kf_chi2_backward_z on a staged plane sample; returns (grad_hit_pos, grad_par, grad_cov or None)
-    shaped like st["hit_pos"], st["par"], st["cov"]."""
+def chi2_backward(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,
+                  ckpt_every: int = 1):
+    """kf_chi2_backward on a staged sample (planes or cylinders, st["geom"]);
+    returns (grad_hit_pos, grad_par, grad_cov or None) shaped like
+    st["hit_pos"], st["par"], st["cov"]."""
     import torch
     _require_cuda(status, grad_chi2, ckpt)
+    gh = torch.empty_like(st["hit_pos"])
+    gp = torch.empty_like(st["par"])
+    gc = torch.empty_like(st["cov"]) if want_cov else None
+    layers = np.ascontiguousarray(st["layers"], np.float32)
+    tn = None if tune is None else ctypes.byref(make_tune(tune))
+    with torch.cuda.device(st["par"].device):
+        rc = lib().kf_chi2_backward(int(st.get("geom", 0)), _ptr(st["par"]), _ptr(st["cov"]), _ptr(st["hit_pos"]),
+                                    _ptr(st["hit_cov"]), layers.ctypes.data_as(ctypes.c_void_p), int(layers.shape[0]),
+                                    int(st["n"]), float(st["bz"]), Layout(*st["layout"]), _ptr(status), _ptr(ckpt),
+                                    int(ckpt_every), _ptr(grad_chi2.contiguous()), _ptr(gh), _ptr(gp), _ptr(gc),
+                                    tn, _stream(stream))
+    _check(rc, "kf_chi2_backward")
+    return gh, gp, gc
+
+
+def chi2_backward_z(st: dict, status, grad_chi2, ckpt=None, want_cov=False, tune=None, stream=None,
+                    ckpt_every: int = 1):
+    """kf_chi2_backward_z (planes) on a staged plane sample; as chi2_backward."""
+    import torch
+    _require_cuda(status, grad_chi2, ckpt)
+    if int(st.get("geom", 0)) != 0:
+        raise ValueError("chi2_backward_z takes a plane sample; use chi2_backward")
     gh = torch.empty_like(st["hit_pos"])
     gp = torch.empty_like(st["par"])
     gc = torch.empty_like(st["cov"]) if want_cov else None
@@ -758,18 +783,20 @@ def _make_autograd():
     import torch
 
     class KFChi2(torch.autograd.Function):
-        """chi2 per track of the plane filter as a differentiable function of
-        the seed parameters and the hit positions (kf_propagate_update_z
-        forward, kf_chi2_backward_z backward).
+        """chi2 per track of the filter as a differentiable function of the
+        seed parameters and the hit positions (kf_propagate_update_z / _r
+        forward, kf_chi2_backward backward).
 
-        apply(par, hit_pos, cov, hit_cov, layer_z, bz, layout, nlay, checkpoint)
-        with tensors in `layout`; checkpoint=True (or a stride s) stores the
-        entering state of every (s-th) layer in the forward, False recomputes
-        them in the backward.
+        apply(par, hit_pos, cov, hit_cov, layers, bz, layout, nlay, checkpoint,
+        geometry) with tensors in `layout`; checkpoint=True (or a stride s)
+        stores the entering state of every (s-th) layer in the forward, False
+        recomputes them in the backward; geometry 0 planes (layers = z), 1
+        cylinders (layers = r).
         """
 
         @staticmethod
-        def forward(ctx, par, hit_pos, cov, hit_cov, layer_z, bz, layout=SOA, nlay=None, checkpoint=True):
+        def forward(ctx, par, hit_pos, cov, hit_cov, layer_z, bz, layout=SOA, nlay=None, checkpoint=True,
+                    geometry=0):
             n = par.shape[-1] if layout[0] == KF_SOA else None
             if n is None:
                 raise ValueError("KFChi2 takes SoA tensors")
@@ -779,9 +806,9 @@ def _make_autograd():
             for t in (par, hit_pos, cov, hit_cov):
                 if t.dtype != torch.float32:
                     raise ValueError("KFChi2 takes float32 tensors")
-            _, _, chi2, status = propagate_update(0, par, cov, hit_pos, hit_cov, layer_z, bz, n, nlay=nlay,
-                                                  layout=layout, ckpt=ck, ckpt_every=every)
-            ctx.meta = {"layers": layer_z, "n": n, "bz": bz, "layout": layout}
+            _, _, chi2, status = propagate_update(int(geometry), par, cov, hit_pos, hit_cov, layer_z, bz, n,
+                                                  nlay=nlay, layout=layout, ckpt=ck, ckpt_every=every)
+            ctx.meta = {"layers": layer_z, "n": n, "bz": bz, "layout": layout, "geom": int(geometry)}
             # saved through autograd, so that an in-place change of an input
             # between forward and backward raises instead of giving wrong
             # gradients (the backward re-reads the inputs)
@@ -794,9 +821,9 @@ def _make_autograd():
         def backward(ctx, grad_chi2):
             par, cov, hit_pos, hit_cov, status = ctx.saved_tensors
             st = dict(ctx.meta, par=par, cov=cov, hit_pos=hit_pos, hit_cov=hit_cov)
-            gh, gp, _ = chi2_backward_z(st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt,
-                                        ckpt_every=ctx.every)
-            return gp, gh, None, None, None, None, None, None, None
+            gh, gp, _ = chi2_backward(st, status, grad_chi2.contiguous().float(), ckpt=ctx.ckpt,
+                                      ckpt_every=ctx.every)
+            return gp, gh, None, None, None, None, None, None, None, None
 
     return KFChi2
 
