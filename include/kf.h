@@ -155,7 +155,9 @@ enum {
  *                     `layout` (per-layer form, E = 27): slot j holds the state
  *                     (6 parameters, then the 21 covariance numbers) that
  *                     entered layer j * ckpt_every; slots of layers a track
- *                     does not reach are left untouched.  Used by kf_chi2_backward_z.
+ *                     does not reach receive unspecified values (with per-track
+ *                     counts in SoA / AoSoA the library writes whole rows).
+ *                     Used by kf_chi2_backward and kf_smooth.
  *   ckpt_every        1, 2, 4, .. 64 (0 means 1): the checkpoint stride in layers
  *                     (anything else: KF_E_SHAPE)
  *   tune              NULL or a launch shape
@@ -265,8 +267,9 @@ kf_status_t kf_propagate_gate_update(int32_t geometry, const float* par_in, cons
  *   smoothed     [n_layers] slots of 27 numbers per track in `layout`
  *                (kf_checkpoint_floats(n, L, 1, layout) floats): slot k
  *                receives the smoothed state on layer k (parameters, then the
- *                packed covariance) for k < applied; other slots are left
- *                untouched.  May be `ckpt` itself (each slot is read before
+ *                packed covariance) for k < applied; other slots receive
+ *                unspecified values (SoA / AoSoA: the library writes whole
+ *                rows).  May be `ckpt` itself (each slot is read before
  *                it is written); must not overlap it otherwise.
  *   tune         NULL or a launch shape (block_threads 64, 128 or 256)
  * Errors: KF_E_SHAPE (geometry, sizes), KF_E_LAYOUT, KF_E_NULL, KF_E_ALIGN,

@@ -59,10 +59,19 @@ struct LaidOutHits {
   }
 };
 
-template <int KIND, bool WIDE, class T = float>
+// FULL: per-track layer counts and checkpoints in an element-major layout
+// -- every lane writes every checkpoint row up to the wave's longest track,
+// nl_wave (slots of a track's unreached layers then hold its final state).
+// Whole rows avoid partially written lines, which memory completes by
+// read-modify-write: the barrel filter with checkpoints went from 1.48 to
+// 0.60 ms (SoA, 960k tracks).  AoS records gain nothing (1.02 -> 1.22 ms):
+// their lines are shared by neighbouring lanes' records either way.
+template <int KIND, bool WIDE, class T = float, bool FULL = false>
 struct LaidOutCkpt {
+  static constexpr bool kFullRows = FULL;
   const StepArgsT<T>& a;
   const Lanes<KIND, WIDE, sizeof(T)>& ln;
+  int nl_wave;
   __device__ __forceinline__ void operator()(int k, const T p[6], const T C[21]) const {
     if (!a.ckpt || (k & ((1 << a.ck_shift) - 1))) return;
     T s[27];
@@ -146,29 +155,36 @@ __device__ __forceinline__ int64_t by_length(const StepArgs& a) {
   return i0 + g * gs + perm[t];
 }
 
-template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM>
+// FULL: checkpoints with per-track layer counts (see LaidOutCkpt).
+template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM, bool FULL = false>
 __global__ void __launch_bounds__(256) KF_STEP_OCCUPANCY kf_step_kernel(const StepArgs a) {
   extern __shared__ float kf_lds[];
   float* ring = kf_lds + __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6)) * kRingFloats;
   int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if constexpr (GEOM == 1 && KF_CYL_SORT > 0) {
+  // (not with checkpoints: a permuted group's two waves would share every
+  // line of the checkpoint rows, each writing half of it at a different time)
+  if constexpr (GEOM == 1 && KF_CYL_SORT > 0 && !FULL) {
     if (a.nlay) i = by_length<KF_CYL_SORT>(a);
   }
+  int nl = 0;
+  if (i < a.n) {
+    nl = a.nlay ? a.nlay[i] : a.L;
+    nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
+  }
+  // every lane is still active here (full blocks): the wave's longest track
+  const int nl_wave = FULL ? wave_max(nl) : 0;
   if (i >= a.n) return;
   const Lanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.Lck);
-  int nl = a.nlay ? a.nlay[i] : a.L;
-  nl = nl < 0 ? 0 : (nl > a.L ? a.L : nl);
   float chi2;
   uint32_t status;
   const LaidOutHits<KIND, WIDE> hits(a, ln, nl);
+  const LaidOutCkpt<KIND, WIDE, float, FULL> ckpt{a, ln, nl_wave};
   if constexpr (ring_staged<GEOM, KIND, WIDE>()) {
     LayerRing<LaidOutHits<KIND, WIDE>, STREAM ? kStreamPolicy : 0> stager(hits, ring);
-    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
-                          a.layer, a.b, chi2, status);
+    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, ckpt, nl, a.layer, a.b, chi2, status);
   } else {
     RegStager<LaidOutHits<KIND, WIDE>> stager(hits);
-    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, LaidOutCkpt<KIND, WIDE>{a, ln}, nl,
-                          a.layer, a.b, chi2, status);
+    run_track<GEOM, PREC>(LaidOutState<KIND, WIDE>{a, ln}, hits, stager, ckpt, nl, a.layer, a.b, chi2, status);
   }
   if (a.chi2) a.chi2[i] = chi2;
   if (a.status) a.status[i] = int32_t(status);
@@ -184,6 +200,9 @@ static hipError_t launch_one(int block, const StepArgs& a, hipStream_t s) {
   if (kStaged && !a.nlay)
     hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE, kStaged>), dim3(unsigned(grid)), dim3(block), lds, s,
                        a);
+  else if (a.ckpt && a.nlay && PREC == PREC_F32 && KIND != KF_AOS)
+    hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE, false, true>), dim3(unsigned(grid)), dim3(block), lds,
+                       s, a);
   else
     hipLaunchKernelGGL((kf_step_kernel<GEOM, PREC, KIND, WIDE, false>), dim3(unsigned(grid)), dim3(block), lds, s, a);
   return hipGetLastError();

@@ -77,10 +77,24 @@ __device__ __forceinline__ void read_slot(const float* slot, int lane, float m[3
 //       must call get() for every layer: the wave's tracks then share one
 //       layer count and a failing track does not leave the loop early
 //   ckpt(k, p, C): called before layer k (may do nothing)
+//   Ckpt::kFullRows: every lane of a wave must call ckpt for every layer up
+//     to the wave's longest track (checkpoint rows are then written whole;
+//     a lane past its own track stores its final state)
 struct NoCkpt {
+  static constexpr bool kFullRows = false;
   template <class T>
   __device__ __forceinline__ void operator()(int, const T*, const T*) const {}
 };
+
+// the largest v over the wave's lanes; every lane of the wave must be active
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    const int o = __shfl_xor(v, d, 64);
+    v = o > v ? o : v;
+  }
+  return v;
+}
 
 // Hits fetched one layer ahead into registers (AoS records: multi-dword loads
 // serve them better than one-dword copies).  hits.next(k): the in-bounds
@@ -179,6 +193,26 @@ __device__ __forceinline__ void run_track(const State& state, const Hits& hits, 
         if (f && !flags) {
           flags = f;
           fail_at = k;
+        }
+      }
+      k = fail_at;
+    } else if constexpr (Ckpt::kFullRows) {
+      // every lane walks as many layers as the wave's longest track so that
+      // each checkpoint row is written by the whole wave (partially written
+      // lines cost a read-modify-write in memory); a lane past its own last
+      // layer, or after its failure, computes nothing and stores its state
+      int fail_at = flags ? 0 : nl;
+      const int nl_w = ckpt.nl_wave;  // the wave's longest track, <= the layer table
+      for (k = 1; k < nl_w; ++k) {
+        const bool act = !flags && k < nl;
+        stager.get(k, m, V);
+        ckpt(k, p, C);
+        if (act) {
+          const uint32_t f = layer_step<GEOM, PREC, GEOM == 0>(p, C, d, m, V, layer[k], b, chi2);
+          if (f) {
+            flags = f;
+            fail_at = k;
+          }
         }
       }
       k = fail_at;

@@ -126,7 +126,9 @@ def test_in_place_and_layouts_agree_bitwise(kf, name):
 
 def test_short_failed_and_empty_tracks(kf):
     """Tracks with 0 or 1 layers, a failure part-way and per-track layer
-    counts: smoothed over exactly the layers applied, other slots untouched."""
+    counts: smoothed over exactly the layers applied (the other slots hold
+    unspecified values: element-major layouts are written in whole rows).
+    In AoS the other slots are not written."""
     s = S.subset(S.generate("p2z_1x8192"), np.arange(200))
     for k in ("hit_cov", "nlay"):
         s[k] = s[k].copy()
@@ -135,22 +137,24 @@ def test_short_failed_and_empty_tracks(kf):
     s["nlay"][5] = 1
     s["nlay"][7] = 9
     sp, sP, ost, _ = _oracle_smooth(s)
-    st = kf.stage_sample(s, kf.SOA)
-    po, co, c2, ss = kf.propagate_update(0, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
-                                         st["bz"], st["n"], nlay=st["nlay"],
-                                         ckpt=(ck := kf.checkpoint_buffer(st["n"], st["L"], kf.SOA, "cuda")))
-    out = torch.full_like(ck, 12345.0)
-    kf.smooth(st, ck, po, co, ss, out=out)
-    torch.cuda.synchronize()
-    gst = ss.cpu().numpy()
-    np.testing.assert_array_equal(gst, ost)
-    gp, gP = kf.smoothed_to_logical(st, out)
-    done = ost >> 16
-    for i in range(200):
-        assert np.all(gp[done[i]:, i] == 12345.0) and np.all(gP[done[i]:, i] == 12345.0)
-    assert done[4] == 0 and done[5] == 1 and done[3] == 6 and done[7] == 9
-    m = metrics(_stack(sp, sP, done), _stack(gp, gP, done), 0)
-    assert_within(m, TOL_SMOOTH_FIT, "short and failed tracks")
+    for lay in (kf.SOA, kf.AOS):
+        st = kf.stage_sample(s, lay)
+        po, co, c2, ss = kf.propagate_update(0, st["par"], st["cov"], st["hit_pos"], st["hit_cov"], st["layers"],
+                                             st["bz"], st["n"], nlay=st["nlay"], layout=lay,
+                                             ckpt=(ck := kf.checkpoint_buffer(st["n"], st["L"], lay, "cuda")))
+        out = torch.full_like(ck, 12345.0)
+        kf.smooth(st, ck, po, co, ss, out=out)
+        torch.cuda.synchronize()
+        gst = ss.cpu().numpy()
+        np.testing.assert_array_equal(gst, ost)
+        gp, gP = kf.smoothed_to_logical(st, out)
+        done = ost >> 16
+        if lay == kf.AOS:
+            for i in range(200):
+                assert np.all(gp[done[i]:, i] == 12345.0) and np.all(gP[done[i]:, i] == 12345.0)
+        assert done[4] == 0 and done[5] == 1 and done[3] == 6 and done[7] == 9
+        m = metrics(_stack(sp, sP, done), _stack(gp, gP, done), 0)
+        assert_within(m, TOL_SMOOTH_FIT, "short and failed tracks")
 
 
 @pytest.mark.parametrize("name,geom", [("p2z_100x9600", 0), ("p2r_100x9600", 1)])
