@@ -351,49 +351,56 @@ __global__ void __launch_bounds__(256) kf_adjoint_kernel(const AdjointArgs a) {
   int done = int(uint32_t(a.status[i]) >> KF_S_LAYERS_SHIFT);
   done = done > L ? L : done;
   const float w = a.grad_chi2[i];
-  const float zero3[3] = {0.0f, 0.0f, 0.0f};
-  for (int k = done; k < L; ++k) ln.template st_all<3>(ln.hp, a.grad_hit, k, zero3);
   float ap[6], aP[21];
 #pragma unroll
   for (int e = 0; e < 6; ++e) ap[e] = 0.0f;
 #pragma unroll
   for (int e = 0; e < 21; ++e) aP[e] = 0.0f;
-  for (int k = done - 1; k >= 0; --k) {
-    // the state entering layer k: from the checkpoint slot that covers it (or
-    // the seed), then forward through layers j0 .. k-1
-    float p[6], P[21];
-    int j0 = 0;
-    if (a.ckpt) {
-      const int c = k >> a.ck_shift;
-      j0 = c << a.ck_shift;
-      float s[27];
-      ln.template ld_all<27>(ln.ck, a.ckpt, c, s);
+  // Layers run in step across the wave (the same k in every lane, lanes past
+  // their track's end idle), so each dL/dm row, hit row and checkpoint row is
+  // one access of the whole wave.  With each lane at its own k the accesses
+  // scatter over rows and every 4-byte word costs a line (10x the bytes on
+  // the barrel sample).  Layers a track did not apply get dL/dm = 0 in the
+  // same store.
+  for (int k = L - 1; k >= 0; --k) {
+    float gm[3] = {0.0f, 0.0f, 0.0f};
+    if (k < done) {
+      // the state entering layer k: from the checkpoint slot that covers it
+      // (or the seed), then forward through layers j0 .. k-1
+      float p[6], P[21];
+      int j0 = 0;
+      if (a.ckpt) {
+        const int c = k >> a.ck_shift;
+        j0 = c << a.ck_shift;
+        float s[27];
+        ln.template ld_all<27>(ln.ck, a.ckpt, c, s);
 #pragma unroll
-      for (int e = 0; e < 6; ++e) p[e] = s[e];
+        for (int e = 0; e < 6; ++e) p[e] = s[e];
 #pragma unroll
-      for (int e = 0; e < 21; ++e) P[e] = s[6 + e];
-    } else {
-      ln.template ld_all<6>(ln.par, a.par_in, 0, p);
-      ln.template ld_all<21>(ln.cov, a.cov_in, 0, P);
-    }
-    if (j0 < k) {
-      float chi2 = 0.0f;
-      Dir d;
-      dir_init(p, d);
-      for (int j = j0; j < k; ++j) {
-        float m[3], V[6];
-        ln.template ld_all<3>(ln.hp, a.hit_pos, j, m);
-        ln.template ld_all<6>(ln.hc, a.hit_cov, j, V);
-        layer_at<GEOM, PREC_F32>(j, p, P, d, m, V, a.layer[j], a.b, chi2);
+        for (int e = 0; e < 21; ++e) P[e] = s[6 + e];
+      } else {
+        ln.template ld_all<6>(ln.par, a.par_in, 0, p);
+        ln.template ld_all<21>(ln.cov, a.cov_in, 0, P);
       }
+      if (j0 < k) {
+        float chi2 = 0.0f;
+        Dir d;
+        dir_init(p, d);
+        for (int j = j0; j < k; ++j) {
+          float m[3], V[6];
+          ln.template ld_all<3>(ln.hp, a.hit_pos, j, m);
+          ln.template ld_all<6>(ln.hc, a.hit_cov, j, V);
+          layer_at<GEOM, PREC_F32>(j, p, P, d, m, V, a.layer[j], a.b, chi2);
+        }
+      }
+      float m[3], V[6];
+      ln.template ld_all<3>(ln.hp, a.hit_pos, k, m);
+      ln.template ld_all<6>(ln.hc, a.hit_cov, k, V);
+      if (GEOM == 0)
+        adjoint_layer_z(p, P, m, V, a.layer[k], a.b, w, ap, aP, gm);
+      else
+        adjoint_layer_r(p, P, m, V, a.layer[k], a.b, w, ap, aP, gm);
     }
-    float m[3], V[6], gm[3];
-    ln.template ld_all<3>(ln.hp, a.hit_pos, k, m);
-    ln.template ld_all<6>(ln.hc, a.hit_cov, k, V);
-    if (GEOM == 0)
-      adjoint_layer_z(p, P, m, V, a.layer[k], a.b, w, ap, aP, gm);
-    else
-      adjoint_layer_r(p, P, m, V, a.layer[k], a.b, w, ap, aP, gm);
     ln.template st_all<3>(ln.hp, a.grad_hit, k, gm);
   }
   ln.template st_all<6>(ln.par, a.grad_par, 0, ap);

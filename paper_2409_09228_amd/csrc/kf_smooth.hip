@@ -280,66 +280,67 @@ __global__ void __launch_bounds__(256) kf_smooth_kernel(const SmoothArgs a) {
         for (int e = 0; e < 6; ++e) nx[e] = 0.0f;
       }
     }
-    if (k >= nd) {
-      // element-major layouts: whole rows -- a lane whose track ends below
-      // layer k writes its final state there, so no line of the output is
-      // written in part (memory completes partial lines by read-modify-write:
-      // 0.94 -> 0.74 ms on the barrel sample; AoS records share their lines
-      // with neighbouring lanes either way and only lose, 0.92 -> 1.09 ms)
-      if constexpr (KIND != KF_AOS) store_state(ln, a.smoothed, k, p1, C);
-      continue;
-    }
-    // cylinder: the prediction into layer k gives layer k's frame and the
-    // Jacobian of the next step back (one propagation per layer and lane,
-    // whichever branch below the lane takes)
-    float dqk[6] = {};
-    CylJac<float> Jk;
-    Frame f0{0.0f, 0.0f};
-    if constexpr (GEOM == 1) {
-      float qk[6];
-      cyl_predict(pm, a.layer[k], a.b, qk, dqk, Jk);
-      f0 = frame_at(qk[0], qk[1]);
-    }
-    if (k == nd - 1) {
-      // the last layer applied: smoothed = filtered
-      store_state(ln, a.smoothed, k, p1, C);
-      if constexpr (GEOM == 1) to_local(f0, C, L5);
-    } else {
-      // step back from layer k + 1 (p1) to layer k (pk)
-      float dp[6];
+    // the row of layer k: the smoothed state, or (k >= nd, element-major
+    // layouts) the track's final state, so that no line of the output is
+    // written in part (memory completes partial lines by read-modify-write:
+    // 0.94 -> 0.74 ms on the barrel sample; AoS records share their lines
+    // with neighbouring lanes either way and only lose, 0.92 -> 1.09 ms).
+    // One store per row after the branches: a store in each branch would
+    // write every row of a divergent wave in two parts at different times.
+    float ps[6];
 #pragma unroll
-      for (int e = 0; e < 6; ++e) dp[e] = p1[e] - pk[e];
-      if constexpr (GEOM == 0) {
-        float dq[6];
-        PlaneJac<float> J;
-        plane_predict(pk, a.layer[k + 1], a.b, dq, J);
-        const PlaneJac<float> G = plane_inverse(J);
-        plane_back(G, dp, dq, D);
-        float Cn[21];
-        transport_plane<true>(G, C, Cn);
-#pragma unroll
-        for (int e = 0; e < 21; ++e) C[e] = Cn[e];
-      } else {
-        const CylInverse G = cyl_inverse(Jn, f0, f1);
-        cyl_back(G, f0, f1, dp, dqn, D);
-        cyl_congruence(G, L5);
-        from_local(f0, L5, C);
+    for (int e = 0; e < 6; ++e) ps[e] = p1[e];
+    if (k < nd) {
+      // cylinder: the prediction into layer k gives layer k's frame and the
+      // Jacobian of the next step back (one propagation per layer and lane,
+      // whichever branch below the lane takes)
+      float dqk[6] = {};
+      CylJac<float> Jk;
+      Frame f0{0.0f, 0.0f};
+      if constexpr (GEOM == 1) {
+        float qk[6];
+        cyl_predict(pm, a.layer[k], a.b, qk, dqk, Jk);
+        f0 = frame_at(qk[0], qk[1]);
       }
-      float ps[6];
+      if (k == nd - 1) {
+        // the last layer applied: smoothed = filtered
+        if constexpr (GEOM == 1) to_local(f0, C, L5);
+      } else {
+        // step back from layer k + 1 (p1) to layer k (pk)
+        float dp[6];
 #pragma unroll
-      for (int e = 0; e < 6; ++e) ps[e] = pk[e] + D[e];
-      store_state(ln, a.smoothed, k, ps, C);
+        for (int e = 0; e < 6; ++e) dp[e] = p1[e] - pk[e];
+        if constexpr (GEOM == 0) {
+          float dq[6];
+          PlaneJac<float> J;
+          plane_predict(pk, a.layer[k + 1], a.b, dq, J);
+          const PlaneJac<float> G = plane_inverse(J);
+          plane_back(G, dp, dq, D);
+          float Cn[21];
+          transport_plane<true>(G, C, Cn);
 #pragma unroll
-      for (int e = 0; e < 6; ++e) p1[e] = pk[e];
+          for (int e = 0; e < 21; ++e) C[e] = Cn[e];
+        } else {
+          const CylInverse G = cyl_inverse(Jn, f0, f1);
+          cyl_back(G, f0, f1, dp, dqn, D);
+          cyl_congruence(G, L5);
+          from_local(f0, L5, C);
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e) ps[e] = pk[e] + D[e];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) p1[e] = pk[e];
+      }
+#pragma unroll
+      for (int e = 0; e < 6; ++e) pk[e] = pm[e];
+      if constexpr (GEOM == 1) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) dqn[e] = dqk[e];
+        Jn = Jk;
+        f1 = f0;
+      }
     }
-#pragma unroll
-    for (int e = 0; e < 6; ++e) pk[e] = pm[e];
-    if constexpr (GEOM == 1) {
-#pragma unroll
-      for (int e = 0; e < 6; ++e) dqn[e] = dqk[e];
-      Jn = Jk;
-      f1 = f0;
-    }
+    if (KIND != KF_AOS || k < nd) store_state(ln, a.smoothed, k, ps, C);
   }
 }
 
