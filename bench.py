@@ -32,18 +32,23 @@ BATCHED_DEFAULT_SHAPE = (128, 1, 1, 2)
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
+# Mean Newton steps of the barrel crossing search per update on the barrel
+# sample (the search stops a lane once its step is below 1e-5 of the path,
+# at most five steps); tests/test_bench.py checks it against the oracle's
+# single-precision search on sampled tracks of that workload.
+NEWTON_STEPS_P2R = 2.17
 # Algorithmic cost of one track-layer update (counted from the method's
 # formulation step by step, FMA = 2 flops, each sin/cos/reciprocal/sqrt =
-# 1 flop).
-FLOPS_PER_UPDATE = {0: 391.0, 1: 890.0}
+# 1 flop).  p2r: 729 flops outside the search's steps plus 27 per step.
+FLOPS_PER_UPDATE = {0: 391.0, 1: round(729.0 + 27.0 * NEWTON_STEPS_P2R, 1)}
 # The VALU side of the roofline charges each transcendental at its cost in
 # FP32 instructions -- a sin/cos pair 40 flops, a reciprocal, division or
 # square root 20: p2z has 3 sin/cos pairs and 1 reciprocal per update
-# (391 - 7 + 3 x 40 + 20 = 524), p2r 8 pairs, 6 reciprocals and 1 square root
-# (890 - 23 + 8 x 40 + 7 x 20 = 1327).  The binding roofline is the one of
-# the two (HBM bytes, charged VALU flops) with the larger fraction of its
-# published peak.
-FLOPS_CHARGED_PER_UPDATE = {0: 524.0, 1: 1327.0}
+# (391 - 7 + 3 x 40 + 20 = 524); p2r 3 pairs and 3 reciprocals or square
+# roots outside the steps and one of each per step (900 + 84 per step).  The
+# binding roofline is the one of the two (HBM bytes, charged VALU flops) with
+# the larger fraction of its published peak.
+FLOPS_CHARGED_PER_UPDATE = {0: 524.0, 1: round(900.0 + 84.0 * NEWTON_STEPS_P2R, 1)}
 FP32_PEAK_NONPACKED_TFLOPS = 78.6  # 256 CU x 64 lanes x 2 flops (FMA) x 2.4 GHz
 PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2409_09228_amd", "csrc")

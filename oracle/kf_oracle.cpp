@@ -34,8 +34,8 @@
 //   Per-track status: bit 0 non-finite value, bit 1 residual covariance not
 //   positive definite, bit 2 surface not reachable (a cylinder beyond the
 //   helix's reach, or a plane parallel to the track's direction), bit 3 the
-//   method's fixed five-step crossing search ends off the cylinder (see
-//   newton_crossing_f32); bits 16..31 hold the number of layers applied.  A track stops at its first failing layer
+//   method's crossing search (at most five Newton steps) ends off the
+//   cylinder (see newton_crossing_f32); bits 16..31 hold the number of layers applied.  A track stops at its first failing layer
 //   and keeps the state from before that layer.  Within a layer the checks
 //   run in this order: surface reachable; the crossing search lands on the
 //   cylinder; hit, propagated state and Jacobian
@@ -213,25 +213,33 @@ template <class S> V6<S> to_plane(const V6<S>& p, double zk, double b, uint32_t&
 }
 
 // The method's own cylinder-crossing search (Sec. 3.2: the barrel
-// propagation is iterative, in a fixed number of steps): start from the
-// straight line's crossing s0 = -beta + sqrt(beta^2 - rho0^2 + rk^2), with
-// beta = x cos(phi) + y sin(phi) and rho0^2 = x^2 + y^2 (s0 = -beta when the
-// square root's argument is negative), then take five Newton steps on
+// propagation is iterative), as the FP32 path runs it: Newton's method on
 // g(s) = x(s)^2 + y(s)^2 - rk^2, g'(s) = 2 (x(s) cos phi(s) + y(s) sin phi(s)).
-// The oracle's crossing is the closed form below; this search only decides
-// status bit 3 (its fifth iterate is off the cylinder: |g| > 2e-4 rk^2, which
-// happens only next to a tangent crossing, where the root is nearly double
-// and Newton's method slows down).  It runs in single precision, the
-// precision of the FP32 path whose flag it mirrors.  Returns the fifth
-// iterate; *rel = |g| / rk^2 there.
+// The start is the root of g's second-order expansion g(0) + 2 beta s + a s^2
+// with beta = x cos(phi) + y sin(phi), gam = y cos(phi) - x sin(phi) and
+// a = 1 + omega gam (clamped to >= 1/2), taken as -g(0) / (beta + sqrt(beta^2
+// - a g(0))); when that denominator is not positive, the straight line's
+// crossing -beta + sqrt(beta^2 - g(0)) (the square roots' arguments clamped at
+// zero).  Then at most five Newton steps, stopping after a step that moves s by
+// no more than 1e-5 |s|.  The oracle's crossing is the closed form below; this
+// search only decides status bit 3 (its last iterate is off the cylinder:
+// |g| > 1e-4 rk^2, which happens only next to a tangent crossing, where the
+// root is nearly double, Newton's method slows down and all five steps run).
+// It runs in single precision, the precision of the FP32 path whose flag it
+// mirrors.  Returns the last iterate; *rel = |g| / rk^2 there; *steps (if not
+// NULL) the number of Newton steps taken.
 inline float newton_crossing_f32(double xd, double yd, double kappa, double phid, double rkd, double bd,
-                                 float* rel) {
+                                 float* rel, int* steps = nullptr) {
   const float x = float(xd), y = float(yd), phi = float(phid), rk = float(rkd);
   const float om = -float(bd) * float(kappa);
   const float c0 = std::cos(phi), s0 = std::sin(phi);
   const float beta = x * c0 + y * s0;
+  const float gam = y * c0 - x * s0;
   const float rk2 = rk * rk;
-  float s = -beta + std::sqrt(std::max(beta * beta - (x * x + y * y) + rk2, 0.0f));
+  const float g0 = x * x + y * y - rk2;
+  const float a = std::max(1.0f + om * gam, 0.5f);
+  const float den = beta + std::sqrt(std::max(beta * beta - a * g0, 0.0f));
+  float s = den > 0.0f ? -g0 / den : -beta + std::sqrt(std::max(beta * beta - g0, 0.0f));
   float X = x, Y = y, cph = c0, sph = s0;
   auto point = [&](float t) {
     const float u = 0.5f * om * t;
@@ -241,17 +249,27 @@ inline float newton_crossing_f32(double xd, double yd, double kappa, double phid
     cph = std::cos(phi + om * t);
     sph = std::sin(phi + om * t);
   };
-  for (int it = 0; it < 5; ++it) {
+  int it = 0;
+  while (it < 5) {
     point(s);
     const float g = X * X + Y * Y - rk2;
     const float gp = 2.0f * (X * cph + Y * sph);
-    s = s - g / gp;
+    const float ds = g / gp;
+    s = s - ds;
+    ++it;
+    if (std::fabs(ds) <= 1e-5f * std::fabs(s)) break;
   }
+  if (steps) *steps = it;
   point(s);
   *rel = std::fabs(X * X + Y * Y - rk2) / rk2;
   return s;
 }
-constexpr float kNewtonResidualMax = 2e-4f;
+// Next to tangency five steps leave a residual of 2.0e-4 .. 2.3e-4 rk^2 (the
+// error only halves per step at a nearly double root); the threshold sits a
+// factor 2 below that cluster, and 4x above the 2.2e-5 of a crossing 1e-3
+// from tangency, so that two single-precision evaluations of the search take
+// the same decision.
+constexpr float kNewtonResidualMax = 1e-4f;
 
 // Propagate to the barrel cylinder r = rk (the "propagation to r" benchmark):
 // the first crossing at s > 0.  The transverse circle has centre
@@ -790,14 +808,17 @@ int kfo_propagate(int geom, const double* p, double target, double bz, double* p
   return 0;
 }
 
-// The method's five-step crossing search on its own (newton_crossing_f32):
-// p [6], cylinder radius rk; returns the fifth iterate s and |g(s)| / rk^2.
-int kfo_newton_r(const double* p, double rk, double bz, double* s_out, double* rel_out) {
+// The method's crossing search on its own (newton_crossing_f32):
+// p [6], cylinder radius rk; returns the last iterate s, |g(s)| / rk^2 and
+// the number of Newton steps taken.
+int kfo_newton_r(const double* p, double rk, double bz, double* s_out, double* rel_out, int32_t* steps_out) {
   float rel = 0.0f;
+  int steps = 0;
   const float s = kfo::newton_crossing_f32(p[kfo::IX], p[kfo::IY], p[kfo::IK], p[kfo::IPHI], rk,
-                                           kfo::kCLight * bz, &rel);
+                                           kfo::kCLight * bz, &rel, &steps);
   *s_out = double(s);
   *rel_out = double(rel);
+  if (steps_out) *steps_out = steps;
   return 0;
 }
 

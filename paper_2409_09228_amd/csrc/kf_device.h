@@ -351,9 +351,8 @@ __device__ __forceinline__ void propagate_z(const T p[6], const T C[21], DirT<T>
 // Reachability in closed form: with rho0^2 = x^2 + y^2 the helix meets the
 // cylinder iff |omega (rk^2 - rho0^2)/2 + x sin(phi) - y cos(phi)| <= rk
 // (for omega -> 0: the line's distance from the axis is at most rk).  The
-// crossing itself: straight-line start s0 = -beta + sqrt(beta^2 - rho0^2 + rk^2),
-// beta = x cos phi + y sin phi, then 5 Newton steps on
-// g(s) = x(s)^2 + y(s)^2 - rk^2, g'(s) = 2 (x(s) cos phi(s) + y(s) sin phi(s)).
+// crossing itself: Newton's method on g(s) = x(s)^2 + y(s)^2 - rk^2 from the
+// root of g's second-order expansion, at most five steps (cylinder_search).
 // The Jacobian adds to the fixed-s partials the path-length term with
 // grad s = -(x J_s[x,:] + y J_s[y,:]) / (x cos phi' + y sin phi'),
 // which keeps the propagated point on the cylinder to first order.
@@ -368,8 +367,28 @@ struct CylJac {
   T x0, x1, x3, x4, y0, y1, y3, y4, z0, z1, z3, z4, z5, f0, f1, f3, f4;
 };
 
-// The search: closed-form reachability, then the path length s from the
-// straight-line start and five Newton steps.  sp, cp: sin and cos of phi.
+// The search: closed-form reachability, then Newton's method for the path
+// length s on g(s) = x(s)^2 + y(s)^2 - rk^2.  With beta = x cos phi + y sin phi
+// and gam = y cos phi - x sin phi (the position along and across the
+// direction), ch = s sinc(u) the chord and u = omega s / 2 half the turning
+// angle, g = g0 + ch (2 (beta cos u + gam sin u) + ch) with g0 = g(0), and
+// g'/2 = beta cos 2u + gam sin 2u + ch cos u: the two constants carry the
+// start point and direction through every step.
+//   Start: the root of the second-order expansion g0 + 2 beta s + a s^2,
+// a = 1 + omega gam (clamped to >= 1/2; written -g0 / (beta + sqrt(.)), which
+// has no cancellation and no division by a); where that denominator is not
+// positive (a crossing inward, or a track on the cylinder already) the
+// straight line's crossing -beta + sqrt(beta^2 - g0) instead.
+//   Steps: at most five; a lane stops after the step that moved s by no more
+// than kSearchTol |s| (then the next step would move it by about
+// |g''/2g'| (kSearchTol s)^2, below the scalar's rounding).  The stop is each
+// lane's own: a track's result never depends on the other tracks of its wave.
+// sp, cp: sin and cos of phi.
+__device__ __forceinline__ float search_tol(float) { return 1e-5f; }
+__device__ __forceinline__ double search_tol(double) { return 1e-9; }
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }  // 1 ulp; a start only
+__device__ __forceinline__ double sqrt_fast(double x) { return sqrt(x); }
+
 template <class T>
 __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T& cp, T rk, T b, bool& reachable) {
   const T om = -b * p[3];
@@ -379,22 +398,35 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
   const T reach = 0.5f * om * (rk2 - rho2) + (x * sp - y * cp);
   reachable = fabs_t(reach) <= rk;
   const T beta = x * cp + y * sp;
-  T s = -beta + sqrt_t(fmax_t(beta * beta - rho2 + rk2, T(0)));
+  const T gam = y * cp - x * sp;
+  const T g0 = rho2 - rk2;
+  const T a = fmax_t(1.0f + om * gam, T(0.5f));
+  const T den = beta + sqrt_fast(fmax_t(beta * beta - a * g0, T(0)));
+  T s = -g0 * rcp_t(den);
+  if (!(den > T(0))) {
+    rare_path();
+    s = -beta + sqrt_fast(fmax_t(beta * beta - g0, T(0)));
+  }
+  const T hom = 0.5f * om;
+  const T tol = search_tol(T(0));
+  bool run = true;
 #pragma unroll
   for (int it = 0; it < 5; ++it) {
-    const T u = 0.5f * om * s;
-    T su, cu, sinc;
-    helix_sinc_t(u, su, cu, sinc);
-    const T cA = cp * cu - sp * su;
-    const T sA = sp * cu + cp * su;
-    const T ch = s * sinc;
-    const T X = x + ch * cA;
-    const T Y = y + ch * sA;
-    const T cP = cA * cu - sA * su;
-    const T sP = sA * cu + cA * su;
-    const T gg = X * X + Y * Y - rk2;
-    const T gp = 2.0f * (X * cP + Y * sP);
-    s = s - gg * rcp_t(gp);
+    if (run) {
+      rare_path();  // a branch, not a select: a wave whose lanes have all stopped skips the step
+      const T u = hom * s;
+      T su, cu, sinc;
+      helix_sinc_t(u, su, cu, sinc);
+      const T ch = s * sinc;
+      const T t = beta * cu + gam * su;
+      const T g = g0 + ch * (2.0f * t + ch);
+      const T c2 = cu * cu - su * su;
+      const T s2 = 2.0f * su * cu;
+      const T gp = 2.0f * (beta * c2 + gam * s2 + ch * cu);
+      const T ds = g * rcp_t(gp);
+      s = s - ds;
+      run = !(fabs_t(ds) <= tol * fabs_t(s));
+    }
   }
   return s;
 }
@@ -403,7 +435,8 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
 // F there, the path length's dependence on p taken from the implicit
 // function x(s)^2 + y(s)^2 = rk^2.  sth, cth, sp, cp: sin and cos of theta
 // and phi of p; sP, cP: of phi at the crossing.  Returns whether the point
-// lies on the cylinder (|x^2 + y^2 - rk^2| <= 2e-4 rk^2).  T: float, or dual
+// lies on the cylinder (|x^2 + y^2 - rk^2| <= 1e-4 rk^2: next to tangency, where
+// the search stops short, its residual clusters at 2.0e-4 .. 2.3e-4 rk^2).  T: float, or dual
 // numbers (then s carries ds/dp); S: the geometry's scalar.
 template <class T, class S>
 __device__ __forceinline__ bool cylinder_at(const T p[6], const T& sth, const T& cth, const T& sp, const T& cp,
@@ -422,7 +455,7 @@ __device__ __forceinline__ bool cylinder_at(const T p[6], const T& sth, const T&
   const T X = x + dx, Y = y + dy;
   cP = cA * cu - sA * su;
   sP = sA * cu + cA * su;
-  const bool on_surface = fabs_t(val(X * X + Y * Y - rk2)) <= decltype(val(rk2))(2.0e-4f) * val(rk2);
+  const bool on_surface = fabs_t(val(X * X + Y * Y - rk2)) <= decltype(val(rk2))(1.0e-4f) * val(rk2);
   const T rsth = rcp_t(sth);
   const T cot = cth * rsth;
   q[0] = X;

@@ -94,7 +94,7 @@ struct LaidOutCkpt {
 
 // How a step kernel fetches its hits.  Planes: the layer step is short, so
 // element-major layouts bring the hits through the per-wave LDS ring with
-// three layers in flight.  Cylinders: five Newton iterations make the step
+// three layers in flight.  Cylinders: the Newton search makes the step
 // long enough for one layer of register prefetch to cover the latency, and
 // each lane then loads only its own hit, without the ring's per-layer copies
 // and LDS reads (5 % faster on the barrel sample in SoA and AoSoA).

@@ -61,3 +61,26 @@ def test_output_errors_report_each_output():
 def test_cpu_identity_is_a_dict():
     info = bench.cpu_identity()
     assert isinstance(info, dict)
+
+
+def test_newton_step_count_matches_the_oracles_search():
+    """The barrel flop count charges NEWTON_STEPS_P2R search steps per update:
+    the mean number of steps the oracle's single-precision search takes on
+    the barrel sample, from the states the FP64 filter enters each layer with
+    (1500 sampled tracks, every layer they apply), within 4 %."""
+    import oracle as O
+    s = S.generate("p2r_100x9600")
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(s["par"].shape[0], 1500, replace=False))
+    sub = S.subset(s, idx)
+    rec = O.filter_record(1, sub["par"], sub["cov"], sub["hit_pos"], sub["hit_cov"], sub["layer_r"],
+                          float(sub["bz"]), nlay=sub["nlay"])
+    steps = []
+    for i in range(len(idx)):
+        for k in range(int(sub["nlay"][i])):
+            p = sub["par"][i] if k == 0 else rec["filt_p"][k - 1, i]
+            steps.append(O.newton_r(p, sub["layer_r"][k], float(sub["bz"]), steps=True)[2])
+    steps = np.asarray(steps)
+    assert steps.min() >= 1 and steps.max() <= 5
+    assert abs(steps.mean() - bench.NEWTON_STEPS_P2R) <= 0.04 * bench.NEWTON_STEPS_P2R, steps.mean()
+    assert bench.FLOPS_PER_UPDATE[1] == round(729.0 + 27.0 * bench.NEWTON_STEPS_P2R, 1)

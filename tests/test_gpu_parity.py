@@ -214,19 +214,20 @@ def test_plane_parallel_track_and_steep_tracks(kf):
 def test_newton_residual_next_to_tangency(kf):
     """Barrel tracks from the origin with radius of curvature R meet a
     cylinder at 2R (1 - eps) at a nearly double root.  From the second
-    cylinder (r = 40 cm) to one at eps = 1e-5 the five Newton steps end off
-    the cylinder (residual ~2.24e-4 r^2 against the 2e-4 r^2 threshold):
+    cylinder (r = 40 cm) to one at eps = 1e-5 the search runs all five Newton
+    steps and ends off the cylinder (residual ~2.0e-4 r^2 against the 1e-4 r^2
+    threshold):
     KF_S_NEWTON_RESIDUAL at that layer, the state frozen after the first two.
     From a cylinder at 155 cm to one at eps = 3e-2 (the direction 14 degrees
     from the surface) they land.  Status words and states as in the oracle,
-    which takes the same five-step decision in single precision.  The seed
+    which takes the same search's decision in single precision.  The seed
     covariance is diag(1e-5), so that the two-hit fit before the flagged
     layer is well conditioned (with diag(1e-4) two hits leave q/pT and phi
     correlated at -0.95, and every FP32 evaluation, the oracle's included, is
     off by ~5e-3 in correlation units).  Closer to tangency the update itself
     is ill-conditioned: measured from 155 cm, the covariance's error in
     correlation units is 2.3e-4 at eps = 3e-2, 6.4e-4 at 1e-2, 5.5e-2 at 3e-3
-    and 1.7 at 1e-3 (there five Newton steps, even in FP64, stop 3.4e-4 cm
+    and 1.7 at 1e-3 (there the search, even in FP64, stops 3.4e-4 cm
     short of the exact crossing)."""
     b = S.C_LIGHT * 3.8
     n = 128
