@@ -167,37 +167,63 @@ __device__ __forceinline__ float fabs_t(float x) { return fabsf(x); }
 __device__ __forceinline__ float val(float x) { return x; }
 __device__ __forceinline__ double val(double x) { return x; }
 
-// The same helpers in FP64 (the full-FP64 form of the step).  sin and cos are
-// the library's; the division is exact IEEE division.  sinc u and G(u) use
-// their Taylor series for |u| < 1/10 -- through u^10, truncation below 1e-22
-// relative -- and the closed forms beyond, where the cancellation in
-// sin u - u cos u (about u^3/3) costs at most 7e-14 relative.  The direction
-// cosines are not carried across layers in FP64: a changed angle is
-// re-evaluated (rotate_by).
+// The same helpers in FP64 (the full-FP64 form of the step).  The division is
+// exact IEEE division.  For |u| < 1/10 sin u, cos u, sinc u and G(u) come from
+// their Taylor series -- through u^10 (G through u^11), truncation below 1e-21
+// relative -- and beyond from the library's sin and cos and the closed forms,
+// where the cancellation in sin u - u cos u (about u^3/3) costs at most 7e-14
+// relative.  The direction's sin and cos are carried across layers as in FP32:
+// an update that moves an angle by |d| <= 1/8 rotates the pair by d (sin d
+// through d^13, cos d through d^14: truncation below 1e-24), a larger one
+// re-evaluates them; the carried pair drifts by about one ulp per layer.
 __device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ double fmax_t(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ double fabs_t(double x) { return fabs(x); }
 __device__ __forceinline__ void helix_sinc_t(double u, double& su, double& cu, double& sinc) {
-  sincos(u, &su, &cu);
   const double u2 = u * u;
-  const double ss =
-      1.0 + u2 * (-1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (-1.0 / 5040.0 + u2 * (1.0 / 362880.0 + u2 * (-1.0 / 39916800.0)))));
-  sinc = fabs(u) < 0.1 ? ss : su / u;
+  if (fabs(u) < 0.1) {
+    sinc = 1.0 + u2 * (-1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (-1.0 / 5040.0 + u2 * (1.0 / 362880.0 + u2 * (-1.0 / 39916800.0)))));
+    su = u * sinc;
+    cu = 1.0 + u2 * (-1.0 / 2.0 + u2 * (1.0 / 24.0 + u2 * (-1.0 / 720.0 + u2 * (1.0 / 40320.0 + u2 * (-1.0 / 3628800.0)))));
+  } else {
+    rare_path();
+    sincos(u, &su, &cu);
+    sinc = su / u;
+  }
 }
 __device__ __forceinline__ void helix_trig_t(double u, double& su, double& cu, double& sinc, double& g) {
   helix_sinc_t(u, su, cu, sinc);
   const double u2 = u * u;
   const double gs = u * (1.0 / 3.0 + u2 * (-1.0 / 30.0 + u2 * (1.0 / 840.0 + u2 * (-1.0 / 45360.0 + u2 * (1.0 / 3991680.0 +
                                                                                        u2 * (-1.0 / 518918400.0))))));
-  g = fabs(u) < 0.1 ? gs : (su - u * cu) / u2;
+  if (fabs(u) < 0.1) {
+    g = gs;
+  } else {
+    rare_path();
+    g = (su - u * cu) / u2;
+  }
 }
 __device__ __forceinline__ void dir_init(const double p[6], DirT<double>& d) {
   sincos(p[4], &d.sp, &d.cp);
   sincos(p[5], &d.st, &d.ct);
 }
-__device__ __forceinline__ void rotate_by(double& s, double& c, double, double angle) { sincos(angle, &s, &c); }
+__device__ __forceinline__ void rotate_by(double& s, double& c, double d, double angle) {
+  if (fabs(d) <= 0.125) {
+    const double d2 = d * d;
+    const double sd =
+        d * (1.0 + d2 * (-1.0 / 6.0 + d2 * (1.0 / 120.0 + d2 * (-1.0 / 5040.0 + d2 * (1.0 / 362880.0 + d2 * (-1.0 / 39916800.0 + d2 * (1.0 / 6227020800.0)))))));
+    const double cd =
+        1.0 + d2 * (-0.5 + d2 * (1.0 / 24.0 + d2 * (-1.0 / 720.0 + d2 * (1.0 / 40320.0 + d2 * (-1.0 / 3628800.0 + d2 * (1.0 / 479001600.0 + d2 * (-1.0 / 87178291200.0)))))));
+    const double sn = s * cd + c * sd;
+    c = c * cd - s * sd;
+    s = sn;
+  } else {
+    rare_path();
+    sincos(angle, &s, &c);
+  }
+}
 
 // The non-trivial entries of the plane Jacobian F:
 //   row x   = e_x + a0 e_z + a1 e_k + a2 e_phi + a3 e_th

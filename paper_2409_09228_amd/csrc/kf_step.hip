@@ -231,9 +231,15 @@ hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a
 
 // ---------------------------------------------------------------- FP64 form
 // The same step in FP64 end to end (arrays, field constant, layer table and
-// arithmetic); hits fetched one layer ahead into registers.
+// arithmetic).  Planes fetch their hits one layer ahead into registers.  The
+// cylinder step's double state needs more than the 256 VGPRs that leave room
+// for two waves per SIMD: it loads each layer's hit when the layer comes and
+// is compiled for two waves per SIMD regardless, spilling a little (one wave
+// per SIMD without spills: 0.91 ms per launch on the barrel sample; two waves
+// with the prefetch: 0.74 ms; two waves, hits loaded on use: 0.71 ms).
 template <int GEOM, int PREC, int KIND>
-__global__ void __launch_bounds__(256) kf_step_kernel_f64(const StepArgsT<double> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+kf_step_kernel_f64(const StepArgsT<double> a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const Lanes<KIND, true, 8> ln(i, a.n, a.L, a.lay, a.Lck);
@@ -242,7 +248,9 @@ __global__ void __launch_bounds__(256) kf_step_kernel_f64(const StepArgsT<double
   double chi2;
   uint32_t status;
   const LaidOutHits<KIND, true, double> hits(a, ln, nl);
-  RegStager<LaidOutHits<KIND, true, double>, double> stager(hits);
+  using Stager = std::conditional_t<GEOM == 1, DirectStager<LaidOutHits<KIND, true, double>, double>,
+                                    RegStager<LaidOutHits<KIND, true, double>, double>>;
+  Stager stager(hits);
   run_track<GEOM, PREC>(LaidOutState<KIND, true, double>{a, ln}, hits, stager, NoCkpt{}, nl, a.layer, a.b, chi2,
                         status);
   if (a.chi2) a.chi2[i] = chi2;

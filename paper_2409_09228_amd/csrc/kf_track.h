@@ -116,6 +116,19 @@ struct RegStager {
   __device__ __forceinline__ void end() {}
 };
 
+// Hits loaded when their layer comes, with nothing held in registers in
+// between: for a step whose own state leaves no room for a prefetched layer
+// (the FP64 cylinder step), where occupancy does the hiding instead.
+template <class Hits, class T = float>
+struct DirectStager {
+  static constexpr bool kCooperative = false;
+  const Hits& h;
+  __device__ __forceinline__ explicit DirectStager(const Hits& h_) : h(h_) {}
+  __device__ __forceinline__ void begin() {}
+  __device__ __forceinline__ void get(int k, T m[3], T V[6]) { h.load(k, m, V); }
+  __device__ __forceinline__ void end() {}
+};
+
 // Element-major hits through this wave's LDS ring (kRingFloats at `ring`).
 // hits.stage<POLICY>(j, slot): start copying the hit of layer min(j, the
 // track's last layer) into the slot (j wave-uniform), with cache policy
