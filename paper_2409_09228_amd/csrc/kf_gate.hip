@@ -25,15 +25,24 @@ namespace {
 // Chi-square of an update of the prediction (q, Pt) with hit (m, V), and
 // whether the candidate takes part (finite, residual covariance positive
 // definite).  R: the arithmetic of the update that follows -- float for the
-// FP32 update (update_f32's expressions), double when S^-1 is taken in FP64
-// (the precision form) -- so the chi-square that decides is the one added.
-template <class R>
+// FP32 update, double when S^-1 is taken in FP64 (the precision form) -- and
+// CHOL its form (update_f32 on cylinders: the Cholesky factor of S), so the
+// chi-square that decides is the one added.
+template <class R, bool CHOL>
 __device__ __forceinline__ bool candidate_chi2(const float q[6], const float Pt[21], const float m[3],
                                                const float V[6], float& chi2) {
   const R r0 = R(m[0] - q[0]), r1 = R(m[1] - q[1]), r2 = R(m[2] - q[2]);
   const R S00 = R(Pt[0] + V[0]), S10 = R(Pt[1] + V[1]), S11 = R(Pt[2] + V[2]);
   const R S20 = R(Pt[3] + V[3]), S21 = R(Pt[4] + V[4]), S22 = R(Pt[5] + V[5]);
   const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
+  if constexpr (CHOL) {
+    const Chol3<R> L = chol3(S00, S10, S11, S20, S21, S22);
+    R z0, z1, z2;
+    L.solve(r0, r1, r2, z0, z1, z2);
+    const R c = z0 * z0 + z1 * z1 + z2 * z2;
+    chi2 = float(c);
+    return in_ok & L.pd & fin(c);
+  }
   const R c00 = S11 * S22 - S21 * S21;
   const R c10 = S20 * S21 - S10 * S22;
   const R c11 = S00 * S22 - S20 * S20;
@@ -123,7 +132,8 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STRE
   for (int j = 0; j < cands.a.M; ++j) {
     float m[3], V[6], c;
     cands.load(k, j, m, V);
-    const bool ok = PREC == PREC_F32 ? candidate_chi2<float>(q, Pt, m, V, c) : candidate_chi2<double>(q, Pt, m, V, c);
+    const bool ok = PREC == PREC_F32 ? candidate_chi2<float, GEOM == 1>(q, Pt, m, V, c)
+                                     : candidate_chi2<double, false>(q, Pt, m, V, c);
     const bool take = ok & (c <= cands.a.gate) & (c < bchi);
     best = take ? j : best;
     bchi = take ? c : bchi;
