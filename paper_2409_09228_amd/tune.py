@@ -29,9 +29,11 @@ BATCHED_SPACE = {
     "waves_mult": (1, 2),
     "layout": ("aos", "soa", "aosoa64"),
 }
-PLAIN_SPACE = {"block": (64, 128, 256), "layout": ("soa", "aos", "aosoa64")}
+# plain step: block size x the layouts, AoSoA with 16 to 128 tracks per block
+PLAIN_SPACE = {"block": (64, 128, 256), "layout": ("soa", "aos", "aosoa16", "aosoa32", "aosoa64", "aosoa128")}
 
-LAYOUTS = {"aos": K.AOS, "soa": K.SOA, "aosoa64": K.aosoa(64)}
+LAYOUTS = {"aos": K.AOS, "soa": K.SOA, "aosoa16": K.aosoa(16), "aosoa32": K.aosoa(32), "aosoa64": K.aosoa(64),
+           "aosoa128": K.aosoa(128)}
 
 
 def default_cache_path() -> str:

@@ -11,7 +11,10 @@ def test_search_space_is_complete():
     c = list(T.candidates(T.BATCHED_SPACE))
     assert len(c) == 3 * 2 * 2 * 2 * 3
     assert {"block": 64, "tpt": 2, "schedule": 1, "waves_mult": 2, "layout": "aosoa64"} in c
-    assert len(list(T.candidates(T.PLAIN_SPACE))) == 9
+    plain = list(T.candidates(T.PLAIN_SPACE))
+    assert len(plain) == 3 * 6
+    assert {c["layout"] for c in plain} == {"soa", "aos", "aosoa16", "aosoa32", "aosoa64", "aosoa128"}
+    assert all(c["layout"] in T.LAYOUTS for c in plain)
 
 
 def test_cache_round_trip(tmp_path):
