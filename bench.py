@@ -900,6 +900,12 @@ def main(argv=None):
         r = time_plain(r_sample, P2R_WORKLOAD, args.layout, 0, args.steps, args.warmup, (args.block, args.tpt))
         out["p2r"] = {"workload": P2R_WORKLOAD, "value": round(r["value"], 1), "unit": "track-layer updates/s",
                       "ms_per_step": round(r["ms_step"], 4), "config": r["config"], "roofline": r["roofline"]}
+        if args.layout != "aos":
+            # the barrel step in AoS records (its fastest layout: each lane's
+            # hit is one contiguous record), same timing procedure
+            ra = time_plain(r_sample, P2R_WORKLOAD, "aos", 0, args.steps, args.warmup, (args.block, args.tpt))
+            out["p2r"]["aos_records"] = {"ms_per_step": round(ra["ms_step"], 4), "value": round(ra["value"], 1)}
+            del ra
     else:
         r_sample, r = None, None
     if not args.no_cpu:

@@ -701,11 +701,14 @@ __device__ __forceinline__ uint32_t update_f32(T q[6], T Pt[21], const T m[3], c
 // covariance update in FP64 too, in plain form or, with JOSEPH, as
 //   P' = (I - K H) Pt (I - K H)^T + K V K^T
 // (symmetric and positive semi-definite by construction).  Bulk state stays FP32.
-template <bool JOSEPH, class T>
+template <bool JOSEPH, bool ZROW, class T>
 __device__ __forceinline__ uint32_t update_f64(T q[6], T Pt[21], const T m[3], const T V[6], T& dchi) {
+  // Pt's entries in double; ZROW (planes): row and column 2 are zero, as
+  // constants, so that every term they enter drops out at compile time
+  auto pt = [&](int i, int j) -> double { return (ZROW && (i == 2 || j == 2)) ? 0.0 : (double)Pt[ix(i, j)]; };
   const double r0 = (double)m[0] - (double)q[0], r1 = (double)m[1] - (double)q[1], r2 = (double)m[2] - (double)q[2];
-  const double S00 = (double)Pt[0] + V[0], S10 = (double)Pt[1] + V[1], S11 = (double)Pt[2] + V[2];
-  const double S20 = (double)Pt[3] + V[3], S21 = (double)Pt[4] + V[4], S22 = (double)Pt[5] + V[5];
+  const double S00 = pt(0, 0) + V[0], S10 = pt(1, 0) + V[1], S11 = pt(1, 1) + V[2];
+  const double S20 = pt(2, 0) + V[3], S21 = pt(2, 1) + V[4], S22 = pt(2, 2) + V[5];
   const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
   const double c00 = S11 * S22 - S21 * S21;
   const double c10 = S20 * S21 - S10 * S22;
@@ -726,7 +729,7 @@ __device__ __forceinline__ uint32_t update_f64(T q[6], T Pt[21], const T m[3], c
   T qn[6], Pn[21];
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
-    const double a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
+    const double a = pt(i, 0), c = pt(i, 1), d = pt(i, 2);
     K0[i] = a * i00 + c * i10 + d * i20;
     K1[i] = a * i10 + c * i11 + d * i21;
     K2[i] = a * i20 + c * i21 + d * i22;
@@ -737,8 +740,7 @@ __device__ __forceinline__ uint32_t update_f64(T q[6], T Pt[21], const T m[3], c
     for (int i = 0; i < 6; ++i)
 #pragma unroll
       for (int j = 0; j <= i; ++j)
-        Pn[ix(i, j)] = (T)((double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] -
-                               K1[i] * (double)Pt[ix(1, j)] - K2[i] * (double)Pt[ix(2, j)]);
+        Pn[ix(i, j)] = (T)(pt(i, j) - K0[i] * pt(0, j) - K1[i] * pt(1, j) - K2[i] * pt(2, j));
   } else {
     const double v00 = V[0], v10 = V[1], v11 = V[2], v20 = V[3], v21 = V[4], v22 = V[5];
 #pragma unroll
@@ -746,9 +748,7 @@ __device__ __forceinline__ uint32_t update_f64(T q[6], T Pt[21], const T m[3], c
       // row i of M = Pt - K Pt_{xyz,:}, then (M - K V)_{i,0:3}
       double M[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j)
-        M[j] = (double)Pt[ix(i, j)] - K0[i] * (double)Pt[ix(0, j)] - K1[i] * (double)Pt[ix(1, j)] -
-               K2[i] * (double)Pt[ix(2, j)];
+      for (int j = 0; j < 6; ++j) M[j] = pt(i, j) - K0[i] * pt(0, j) - K1[i] * pt(1, j) - K2[i] * pt(2, j);
       const double e0 = M[0] - (K0[i] * v00 + K1[i] * v10 + K2[i] * v20);
       const double e1 = M[1] - (K0[i] * v10 + K1[i] * v11 + K2[i] * v21);
       const double e2 = M[2] - (K0[i] * v20 + K1[i] * v21 + K2[i] * v22);
@@ -773,8 +773,8 @@ enum { PREC_F32 = 0, PREC_F64 = 1, PREC_F64_JOSEPH = 2 };
 template <int GEOM, int PREC, class T>
 __device__ __forceinline__ uint32_t update(T q[6], T Pt[21], const T m[3], const T V[6], T& dchi) {
   if (PREC == PREC_F32) return update_f32<GEOM == 0, T>(q, Pt, m, V, dchi);
-  if (PREC == PREC_F64) return update_f64<false, T>(q, Pt, m, V, dchi);
-  return update_f64<true, T>(q, Pt, m, V, dchi);
+  if (PREC == PREC_F64) return update_f64<false, GEOM == 0, T>(q, Pt, m, V, dchi);
+  return update_f64<true, GEOM == 0, T>(q, Pt, m, V, dchi);
 }
 
 // ZIN (planes): C has the zero z row and column a plane update leaves.
