@@ -123,7 +123,8 @@ enum {
   KF_S_NO_CROSSING = 4,     /* the helix never reaches the surface: a cylinder beyond its
                                reach, or a plane parallel to its direction
                                (|cos theta| < 1e-6) */
-  KF_S_NEWTON_RESIDUAL = 8, /* the cylinder iteration ended off the surface */
+  KF_S_NEWTON_RESIDUAL = 8, /* the cylinder iteration ended off the surface, or
+                               on a crossing other than the first ahead */
   KF_S_BAD_HITS = 16        /* kf_propagate_update_batched: the track's hit rows fall
                                outside [0, n_hits); the track is left as it came in */
 };
@@ -178,11 +179,16 @@ kf_status_t kf_propagate_update_z(
  * kf_propagate_update_r -- the same through barrel cylinders r = layer_r[l]
  * (Sec. 3.2, "propagation to r": an iterative approach that advances the
  * track state to the next radius).  The crossing is the first one at positive
- * path length; it is found from a straight-line start by five Newton steps on
- * x(s)^2 + y(s)^2 - r^2, after a closed-form test that the helix reaches the
- * cylinder at all (KF_S_NO_CROSSING otherwise).  A crossing whose radius still
- * misses r_l by more than 1e-4 * r_l after the five steps sets
- * KF_S_NEWTON_RESIDUAL.  Arguments as kf_propagate_update_z (the checkpoints
+ * path length; it is found by Newton steps on g(s) = x(s)^2 + y(s)^2 - r^2
+ * from the first positive root of g's second-order expansion (at most five
+ * steps; a track stops once its steps have converged), after a closed-form
+ * test that the helix reaches the cylinder at all (KF_S_NO_CROSSING
+ * otherwise).  Layers may lie inside the track (decreasing radii): the search
+ * then starts at the near root.  KF_S_NEWTON_RESIDUAL (and the track stops
+ * there) when the last iterate misses the cylinder by more than
+ * |g| = 1e-4 r^2 (a radius off by about 5e-5 r: next to tangency), or is not
+ * the first crossing ahead (g' not of the opposite sign to g(0), s <= 0, or
+ * a full turn made: strongly curved tracks entering a cylinder).  Arguments as kf_propagate_update_z (the checkpoints
  * feed kf_smooth); the longer barrel step prefetches each lane's hits into
  * registers in every layout, so the non-temporal form of the planes does not
  * apply here.

@@ -71,7 +71,7 @@ def lib():
         L.kfo_run_f32.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, f, f, f, f, c_int, f, f, f, i32, c_int]
         L.kfo_propagate.argtypes = [c_int, d, c_dbl, c_dbl, d, d, u32]
         L.kfo_update.argtypes = [d, d, d, d, c_int, d, d, d, u32]
-        L.kfo_newton_r.argtypes = [d, c_dbl, c_dbl, d, d, ctypes.POINTER(ctypes.c_int32)]
+        L.kfo_newton_r.argtypes = [d, c_dbl, c_dbl, d, d, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.kfo_grad_chi2.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, c_int]
         L.kfo_grad_chi2_f32.argtypes = L.kfo_grad_chi2.argtypes
         L.kfo_filter_record.argtypes = [c_int, c_i64, c_int, d, c_dbl, i32, d, d, d, d, c_int, d, d, d, d, d, d,
@@ -150,15 +150,17 @@ def propagate(geom: int, p, target: float, bz: float):
 def newton_r(p, rk: float, bz: float, steps: bool = False):
     """The method's crossing search for cylinder rk on its own (single
     precision): (last iterate s, |x(s)^2 + y(s)^2 - rk^2| / rk^2), plus the
-    number of Newton steps taken if `steps`.  The oracle's crossing is the
-    closed form; this search decides the ST_NEWTON_RESIDUAL flag."""
+    number of Newton steps taken and whether the iterate is the first
+    crossing if `steps`.  The oracle's crossing is the closed form; this
+    search decides the ST_NEWTON_RESIDUAL flag."""
     p = np.ascontiguousarray(p, np.float64)
     s = ctypes.c_double(0.0)
     rel = ctypes.c_double(0.0)
     n = ctypes.c_int32(0)
+    first = ctypes.c_int32(0)
     lib().kfo_newton_r(_p(p, ctypes.c_double), float(rk), float(bz), ctypes.byref(s), ctypes.byref(rel),
-                       ctypes.byref(n))
-    return (s.value, rel.value, n.value) if steps else (s.value, rel.value)
+                       ctypes.byref(n), ctypes.byref(first))
+    return (s.value, rel.value, n.value, bool(first.value)) if steps else (s.value, rel.value)
 
 
 def update(p, P21, m, V6, joseph=False):

@@ -215,21 +215,34 @@ template <class S> V6<S> to_plane(const V6<S>& p, double zk, double b, uint32_t&
 // The method's own cylinder-crossing search (Sec. 3.2: the barrel
 // propagation is iterative), as the FP32 path runs it: Newton's method on
 // g(s) = x(s)^2 + y(s)^2 - rk^2, g'(s) = 2 (x(s) cos phi(s) + y(s) sin phi(s)).
-// The start is the root of g's second-order expansion g(0) + 2 beta s + a s^2
-// with beta = x cos(phi) + y sin(phi), gam = y cos(phi) - x sin(phi) and
-// a = 1 + omega gam (clamped to >= 1/2), taken as -g(0) / (beta + sqrt(beta^2
-// - a g(0))); when that denominator is not positive, the straight line's
-// crossing -beta + sqrt(beta^2 - g(0)) (the square roots' arguments clamped at
-// zero).  Then at most five Newton steps, stopping after a step that moves s by
-// no more than 1e-5 |s|.  The oracle's crossing is the closed form below; this
+// The start is the first positive root of g's second-order expansion
+// g(0) + 2 beta s + a s^2 with beta = x cos(phi) + y sin(phi),
+// gam = y cos(phi) - x sin(phi) and a = 1 + omega gam (clamped to >= 1/2), in
+// forms free of cancellation: from inside the cylinder (g(0) < 0) the positive
+// root -g(0) / (beta + sqrt(beta^2 - a g(0))), from outside (g(0) > 0, moving
+// inward) the near root g(0) / (sqrt(beta^2 - a g(0)) - beta); when that
+// denominator is not positive, the straight line's crossing
+// -beta + sqrt(beta^2 - g(0)) (square roots' arguments clamped at zero).
+// Then at most five Newton steps, stopping after a step that moves s by no
+// more than 1e-5 |s| and by no more than a tenth of the step before it (the
+// quadratic regime, where the next step would be some 1e-7 of s at most;
+// next to a double root the error only halves per step and all five steps
+// run).  The oracle's crossing is the closed form below; this
 // search only decides status bit 3 (its last iterate is off the cylinder:
 // |g| > 1e-4 rk^2, which happens only next to a tangent crossing, where the
-// root is nearly double, Newton's method slows down and all five steps run).
-// It runs in single precision, the precision of the FP32 path whose flag it
-// mirrors.  Returns the last iterate; *rel = |g| / rk^2 there; *steps (if not
-// NULL) the number of Newton steps taken.
+// root is nearly double, Newton's method slows down and all five steps run),
+// or the iterate is not the first crossing: there g'(s) has the opposite sign
+// to g(0) (g rises through zero from inside the cylinder and falls through it
+// from outside), it lies ahead (s > 0) and the helix has not yet completed a
+// turn (|omega s| < 2 pi); an iterate where any fails is another crossing (a
+// strongly curved track entering a cylinder, whose second-order start lies
+// past the first crossing and whose steps may run on to a crossing behind
+// the track, or one that loops round and enters again).  It runs in single precision, the precision of
+// the FP32 path whose flag it mirrors.  Returns the last iterate; *rel =
+// |g| / rk^2 there; *steps (if not NULL) the number of Newton steps taken;
+// *first (if not NULL) whether the iterate is the first crossing.
 inline float newton_crossing_f32(double xd, double yd, double kappa, double phid, double rkd, double bd,
-                                 float* rel, int* steps = nullptr) {
+                                 float* rel, int* steps = nullptr, bool* first = nullptr) {
   const float x = float(xd), y = float(yd), phi = float(phid), rk = float(rkd);
   const float om = -float(bd) * float(kappa);
   const float c0 = std::cos(phi), s0 = std::sin(phi);
@@ -238,8 +251,10 @@ inline float newton_crossing_f32(double xd, double yd, double kappa, double phid
   const float rk2 = rk * rk;
   const float g0 = x * x + y * y - rk2;
   const float a = std::max(1.0f + om * gam, 0.5f);
-  const float den = beta + std::sqrt(std::max(beta * beta - a * g0, 0.0f));
-  float s = den > 0.0f ? -g0 / den : -beta + std::sqrt(std::max(beta * beta - g0, 0.0f));
+  const float sq = std::sqrt(std::max(beta * beta - a * g0, 0.0f));
+  const bool inward = g0 > 0.0f;
+  const float den = inward ? sq - beta : beta + sq;
+  float s = den > 0.0f ? (inward ? g0 : -g0) / den : -beta + std::sqrt(std::max(beta * beta - g0, 0.0f));
   float X = x, Y = y, cph = c0, sph = s0;
   auto point = [&](float t) {
     const float u = 0.5f * om * t;
@@ -250,6 +265,7 @@ inline float newton_crossing_f32(double xd, double yd, double kappa, double phid
     sph = std::sin(phi + om * t);
   };
   int it = 0;
+  float prev = 0.0f;  // the step before (none yet: no stop after the first)
   while (it < 5) {
     point(s);
     const float g = X * X + Y * Y - rk2;
@@ -257,11 +273,14 @@ inline float newton_crossing_f32(double xd, double yd, double kappa, double phid
     const float ds = g / gp;
     s = s - ds;
     ++it;
-    if (std::fabs(ds) <= 1e-5f * std::fabs(s)) break;
+    if (std::fabs(ds) <= 1e-5f * std::fabs(s) && std::fabs(ds) <= 0.1f * std::fabs(prev)) break;
+    prev = ds;
   }
   if (steps) *steps = it;
   point(s);
   *rel = std::fabs(X * X + Y * Y - rk2) / rk2;
+  const float gs = X * cph + Y * sph;
+  if (first) *first = (g0 > 0.0f ? gs < 0.0f : gs > 0.0f) && s > 0.0f && std::fabs(om * s) < 6.2831853f;
   return s;
 }
 // Next to tangency five steps leave a residual of 2.0e-4 .. 2.3e-4 rk^2 (the
@@ -310,8 +329,9 @@ template <class S> V6<S> to_cylinder(const V6<S>& p, double rk, double b, uint32
   // the crossing exists; flag it if the method's own search misses it (the
   // state returned is still the exact crossing)
   float rel;
-  newton_crossing_f32(val(p[IX]), val(p[IY]), val(p[IK]), val(p[IPHI]), rk, b, &rel);
-  if (!(rel <= kNewtonResidualMax)) flags |= ST_NEWTON_RESIDUAL;
+  bool first = true;
+  newton_crossing_f32(val(p[IX]), val(p[IY]), val(p[IK]), val(p[IPHI]), rk, b, &rel, nullptr, &first);
+  if (!(rel <= kNewtonResidualMax) || !first) flags |= ST_NEWTON_RESIDUAL;
   return helix_at(p, s, b);
 }
 
@@ -809,16 +829,19 @@ int kfo_propagate(int geom, const double* p, double target, double bz, double* p
 }
 
 // The method's crossing search on its own (newton_crossing_f32):
-// p [6], cylinder radius rk; returns the last iterate s, |g(s)| / rk^2 and
-// the number of Newton steps taken.
-int kfo_newton_r(const double* p, double rk, double bz, double* s_out, double* rel_out, int32_t* steps_out) {
+// p [6], cylinder radius rk; returns the last iterate s, |g(s)| / rk^2, the
+// number of Newton steps taken and whether the iterate is the first crossing.
+int kfo_newton_r(const double* p, double rk, double bz, double* s_out, double* rel_out, int32_t* steps_out,
+                 int32_t* first_out) {
   float rel = 0.0f;
   int steps = 0;
+  bool first = true;
   const float s = kfo::newton_crossing_f32(p[kfo::IX], p[kfo::IY], p[kfo::IK], p[kfo::IPHI], rk,
-                                           kfo::kCLight * bz, &rel, &steps);
+                                           kfo::kCLight * bz, &rel, &steps, &first);
   *s_out = double(s);
   *rel_out = double(rel);
   if (steps_out) *steps_out = steps;
+  if (first_out) *first_out = first ? 1 : 0;
   return 0;
 }
 

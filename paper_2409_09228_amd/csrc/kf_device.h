@@ -400,15 +400,20 @@ struct CylJac {
 // angle, g = g0 + ch (2 (beta cos u + gam sin u) + ch) with g0 = g(0), and
 // g'/2 = beta cos 2u + gam sin 2u + ch cos u: the two constants carry the
 // start point and direction through every step.
-//   Start: the root of the second-order expansion g0 + 2 beta s + a s^2,
-// a = 1 + omega gam (clamped to >= 1/2; written -g0 / (beta + sqrt(.)), which
-// has no cancellation and no division by a); where that denominator is not
-// positive (a crossing inward, or a track on the cylinder already) the
+//   Start: the first positive root of g's second-order expansion
+// g0 + 2 beta s + a s^2, a = 1 + omega gam (clamped to >= 1/2), in forms with
+// no cancellation and no division by a: from inside the cylinder (g0 < 0)
+// -g0 / (beta + sqrt(beta^2 - a g0)), from outside moving inward (g0 > 0) the
+// near root g0 / (sqrt(beta^2 - a g0) - beta); where that denominator is not
+// positive (moving away from the cylinder, or on it moving inward) the
 // straight line's crossing -beta + sqrt(beta^2 - g0) instead.
-//   Steps: at most five; a lane stops after the step that moved s by no more
-// than kSearchTol |s| (then the next step would move it by about
-// |g''/2g'| (kSearchTol s)^2, below the scalar's rounding).  The stop is each
-// lane's own: a track's result never depends on the other tracks of its wave.
+//   Steps: at most five; a lane stops after a step that moved s by no more
+// than search_tol |s| and by no more than a tenth of the step before it: the
+// quadratic regime, where the next step would move s by about the ratio
+// times this step's relative size, 1e-2 search_tol |s| at most, below the
+// scalar's rounding.  Next to a double root the error only halves per step,
+// the ratio stays near 1/2 and all five steps run.  The stop is each lane's
+// own: a track's result never depends on the other tracks of its wave.
 // sp, cp: sin and cos of phi.
 __device__ __forceinline__ float search_tol(float) { return 1e-5f; }
 __device__ __forceinline__ double search_tol(double) { return 1e-9; }
@@ -427,14 +432,17 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
   const T gam = y * cp - x * sp;
   const T g0 = rho2 - rk2;
   const T a = fmax_t(1.0f + om * gam, T(0.5f));
-  const T den = beta + sqrt_fast(fmax_t(beta * beta - a * g0, T(0)));
-  T s = -g0 * rcp_t(den);
+  const T sq = sqrt_fast(fmax_t(beta * beta - a * g0, T(0)));
+  const bool inward = g0 > T(0);
+  const T den = inward ? sq - beta : beta + sq;
+  T s = (inward ? g0 : -g0) * rcp_t(den);
   if (!(den > T(0))) {
     rare_path();
     s = -beta + sqrt_fast(fmax_t(beta * beta - g0, T(0)));
   }
   const T hom = 0.5f * om;
   const T tol = search_tol(T(0));
+  T prev = T(0);  // the step before (none yet: no stop after the first)
   bool run = true;
 #pragma unroll
   for (int it = 0; it < 5; ++it) {
@@ -451,7 +459,8 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
       const T gp = 2.0f * (beta * c2 + gam * s2 + ch * cu);
       const T ds = g * rcp_t(gp);
       s = s - ds;
-      run = !(fabs_t(ds) <= tol * fabs_t(s));
+      run = !((fabs_t(ds) <= tol * fabs_t(s)) & (fabs_t(ds) <= T(0.1f) * fabs_t(prev)));
+      prev = ds;
     }
   }
   return s;
@@ -527,7 +536,18 @@ __device__ __forceinline__ uint32_t helix_to_cylinder(const T p[6], DirT<T>& d, 
   const bool on_surface = cylinder_at<T, T>(p, d.st, d.ct, d.sp, d.cp, s, rk, b, q, J, sP, cP, inc);
   d.cp = cP;
   d.sp = sP;
-  return !reachable ? S_NO_CROSSING : (!on_surface ? S_NEWTON : 0u);
+  // the first crossing: g' = 2 (x cos phi + y sin phi) there has the opposite
+  // sign to g(0) (g rises through zero from inside the cylinder, falls
+  // through it from outside), it lies ahead (s > 0) and the helix has not
+  // completed a turn (|omega s| < 2 pi); an iterate where any fails is
+  // another crossing (a strongly curved track entering a cylinder, whose
+  // start lay past the first crossing and whose steps may run on to a
+  // crossing behind the track, or one that loops round and enters again),
+  // reported like a search that did not land
+  const T gs = q[0] * cP + q[1] * sP;
+  const bool first = (p[0] * p[0] + p[1] * p[1] > rk * rk ? gs < T(0) : gs > T(0)) & (s > T(0)) &
+                     (fabs_t(b * p[3] * s) < T(6.2831853f));
+  return !reachable ? S_NO_CROSSING : (!(on_surface & first) ? S_NEWTON : 0u);
 }
 
 // Pt = F C F^T for the cylinder Jacobian, on packed covariances.

@@ -257,6 +257,45 @@ def test_newton_residual_next_to_tangency(kf):
         assert_within(m, TOL_F32, f"tangent layer at r = {layers[-1]:.3f}")
 
 
+def test_inward_barrel_layers(kf):
+    """Layers at decreasing radii: barrel tracks of the sample taken at their
+    r = 40 cm crossing and reversed (charge, direction and polar angle), run
+    inward through r = 25 and 10 cm on exact hits (7 % are flagged at the
+    first).  From outside a cylinder
+    the search starts at the near root; strongly curved tracks whose search
+    converges on a later crossing are flagged (status bit 3) by the kernels
+    and by the oracle's single-precision search alike.  Status words as in
+    the oracle (some flagged), states within the calibrated FP32 gates."""
+    r = S.generate("p2r_100x9600", n_events=1)
+    sel = np.nonzero(r["nlay"] >= 8)[0][:4096]
+    rev = np.empty((len(sel), 6))
+    for j, i in enumerate(sel):
+        po, _, _ = O.propagate(1, r["truth"][i], r["layer_r"][7], 3.8)
+        rev[j] = po
+    rev[:, 3], rev[:, 4], rev[:, 5] = -rev[:, 3], rev[:, 4] + np.pi, np.pi - rev[:, 5]
+    layers = np.array([r["layer_r"][4], r["layer_r"][1]])
+    hp = np.stack([S.truth_cross_cylinder(rev, rk, 3.8) for rk in layers])
+    reach = np.isfinite(hp).all(axis=2)
+    nlay = np.where(reach[0], np.where(reach[1], 2, 1), 0).astype(np.int32)
+    assert layers[0] == 25.0 and layers[1] == 10.0
+    hp = np.nan_to_num(hp)
+    n, L = len(sel), 2
+    s = {"name": "inward", "par": rev.copy(), "cov": S.diag_packed(6, 1e-5, n), "truth": rev,
+         "hit_pos": hp, "hit_cov": np.broadcast_to(S.diag_packed(3, 1e-4, 1)[None], (L, n, 6)).copy(),
+         "layer_z": layers, "layer_r": layers, "nlay": nlay,
+         "geom": np.full(n, 1, np.uint8), "bz": 3.8}
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    flagged = (ref[3] & O.ST_NEWTON_RESIDUAL) != 0
+    print("inward: tracks", n, "two layers", int((nlay == 2).sum()), "flagged", int(flagged.sum()))
+    assert flagged.sum() > 0 and (ref[3] >> 16).sum() > 0.8 * nlay.sum()
+    m = metrics(ref, got, 1)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), 1)
+    print(m, f32)
+    assert_within(m, calibrated(TOL_F32, f32), "inward barrel layers")
+
+
 def test_max_layers(kf):
     """64 planes (the longest layer table), z_k = 10 + 5k."""
     w = S.Workload("p2z_64", "z", 1, 512, 64, seed_index=9)

@@ -334,6 +334,52 @@ def test_newton_residual_flag_next_to_tangency(kappa, phi):
             assert rel < 0.25 * 1e-4
 
 
+def _reversed_at(t, r_out):
+    """The barrel track t at its crossing with r_out, running backwards
+    (charge, direction and polar angle reversed): it now enters the cylinders
+    inside r_out."""
+    po, _, _ = O.propagate(1, t, r_out, B38)
+    rev = po.copy()
+    rev[3], rev[4], rev[5] = -po[3], po[4] + np.pi, np.pi - po[5]
+    return rev
+
+
+def test_inward_crossings_land_on_the_first_or_are_flagged():
+    """From outside a cylinder the search starts at the near root of g's
+    second-order expansion; a strongly curved track can still converge on a
+    later crossing, and the search then reports itself (status bit 3: g'
+    with the sign of g(0), or a full turn made).  Reversed barrel tracks from
+    r = 40 cm to r = 20 cm: every crossing is flagged or lands on the
+    cylinder; one that converged (stopped before the fifth step) lies within
+    5e-6 of the closed-form first crossing; most land, 95 % of those
+    converge (the rest, strongly curved, run out of steps on the cylinder),
+    and some of the strongly curved ones (turning by more than a radian)
+    are flagged."""
+    r = S.generate("p2r_100x9600", n_events=1)
+    rng = np.random.default_rng(3)
+    idx = [i for i in rng.choice(r["par"].shape[0], 1500, replace=False) if r["nlay"][i] >= 8]
+    landed = flagged = converged = 0
+    for i in idx:
+        rev = _reversed_at(r["truth"][i], r["layer_r"][7])
+        rk = r["layer_r"][3]
+        pin, _, fl = O.propagate(1, rev, rk, B38)
+        if fl & O.ST_NO_CROSSING:
+            continue
+        s0 = (pin[4] - rev[4]) / (-b38 * rev[3])
+        sn, rel, n, first = O.newton_r(rev, rk, B38, steps=True)
+        if rel > 1e-4 or not first:
+            flagged += 1
+            assert fl & O.ST_NEWTON_RESIDUAL
+        else:
+            landed += 1
+            assert fl == 0
+            if n < 5:
+                converged += 1
+                assert abs(sn - s0) <= 5e-6 * s0, (sn, s0)
+    assert landed >= 0.8 * (landed + flagged) and flagged > 0, (landed, flagged)
+    assert converged >= 0.9 * landed, (converged, landed)
+
+
 def test_filter_stops_at_a_tangent_layer():
     """The filter stops with the residual flag at the layer the search
     misses and keeps the state from before it."""
