@@ -161,8 +161,11 @@ __device__ __forceinline__ uint32_t gate_layer(const Candidates<KIND, WIDE, STRE
 
 }  // namespace
 
+// Cylinders: compiled for 4 waves per SIMD (142 VGPRs and 3 waves otherwise;
+// at 4 it spills 24 bytes per lane: 1.380 -> 1.326 ms on the barrel sample).
 template <int GEOM, int PREC, int KIND, bool WIDE, bool STREAM>
-__global__ void __launch_bounds__(256) kf_gate_kernel(const GateArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEOM == 1 && PREC == 0 ? 4 : 1, 8)))
+kf_gate_kernel(const GateArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const GateLanes<KIND, WIDE, STREAM> ln(i, a.n, a.L, a.lay);

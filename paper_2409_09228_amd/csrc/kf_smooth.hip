@@ -244,8 +244,11 @@ __device__ __forceinline__ void store_state(const SmoothLanes<KIND, WIDE>& ln, f
 
 }  // namespace
 
+// Cylinders: compiled for 4 waves per SIMD (128 VGPRs, no spill; 156 and 3
+// waves otherwise: 557 -> 551 us on the barrel sample).
 template <int GEOM, int KIND, bool WIDE>
-__global__ void __launch_bounds__(256) kf_smooth_kernel(const SmoothArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GEOM == 1 ? 4 : 1, 8)))
+kf_smooth_kernel(const SmoothArgs a) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= a.n) return;
   const SmoothLanes<KIND, WIDE> ln(i, a.n, a.L, a.lay, a.L);
