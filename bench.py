@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "track-layer updates/sec (propagate+Kalman) FP32 at 1 GPU; % of HBM/VALU roofline"
 DEFAULT_WORKLOAD = "p2z_100x9600"
 P2R_WORKLOAD = "p2r_100x9600"
+P2R_LAYOUT = "aos"  # the barrel step's fastest layout (the autotuner's pick on the barrel sample)
 HBM_PEAK_GBS = 8000.0
 # kf_propagate_update_batched's launch shape when none is given (block,
 # tracks per thread, schedule, grid multiple), as include/kf.h states it
@@ -894,18 +895,21 @@ def main(argv=None):
         "roofline": head["roofline"],
     }
     # the barrel form beside the headline plane form: same launch shape, same
-    # timing procedure, its own roofline
+    # timing procedure, its own roofline; in AoS records, its fastest layout
+    # (each lane's hit is one contiguous record; the autotuner's pick), with
+    # the headline's layout timed beside it
     if not args.no_p2r and args.workload == DEFAULT_WORKLOAD and args.flags == 0:
         r_sample = S.generate(P2R_WORKLOAD)
-        r = time_plain(r_sample, P2R_WORKLOAD, args.layout, 0, args.steps, args.warmup, (args.block, args.tpt))
+        r_layout = P2R_LAYOUT if args.layout == "soa" else args.layout
+        r = time_plain(r_sample, P2R_WORKLOAD, r_layout, 0, args.steps, args.warmup, (args.block, args.tpt))
         out["p2r"] = {"workload": P2R_WORKLOAD, "value": round(r["value"], 1), "unit": "track-layer updates/s",
                       "ms_per_step": round(r["ms_step"], 4), "config": r["config"], "roofline": r["roofline"]}
-        if args.layout != "aos":
-            # the barrel step in AoS records (its fastest layout: each lane's
-            # hit is one contiguous record), same timing procedure
-            ra = time_plain(r_sample, P2R_WORKLOAD, "aos", 0, args.steps, args.warmup, (args.block, args.tpt))
-            out["p2r"]["aos_records"] = {"ms_per_step": round(ra["ms_step"], 4), "value": round(ra["value"], 1)}
-            del ra
+        if r_layout != args.layout:
+            rh = time_plain(r_sample, P2R_WORKLOAD, args.layout, 0, args.steps, args.warmup, (args.block, args.tpt))
+            out["p2r"]["in_headline_layout"] = {"layout": args.layout, "ms_per_step": round(rh["ms_step"], 4),
+                                                "value": round(rh["value"], 1),
+                                                "roofline_frac": rh["roofline"]["frac"]}
+            del rh
     else:
         r_sample, r = None, None
     if not args.no_cpu:
