@@ -35,10 +35,12 @@
 //   positive definite, bit 2 surface not reachable (a cylinder beyond the
 //   helix's reach, or a plane parallel to the track's direction), bit 3 the
 //   method's crossing search (at most five Newton steps) ends off the
-//   cylinder (see newton_crossing_f32); bits 16..31 hold the number of layers applied.  A track stops at its first failing layer
-//   and keeps the state from before that layer.  Within a layer the checks
-//   run in this order: surface reachable; the crossing search lands on the
-//   cylinder; hit, propagated state and Jacobian
+//   cylinder or on a crossing other than the first ahead (see
+//   newton_crossing_f32); bits 16..31 hold the number of layers applied.  A
+//   track stops at its first failing layer and keeps the state from before
+//   that layer.  Within a layer the checks run in this order: surface
+//   reachable; the crossing search lands on the first crossing; hit,
+//   propagated state and Jacobian
 //   finite; residual covariance positive definite; updated state finite.
 //   Process noise is zero (no material effects).
 
