@@ -13,6 +13,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace kf {
 
@@ -655,7 +656,10 @@ __device__ __forceinline__ uint32_t update_f32(T q[6], T Pt[21], const T m[3], c
   const T S20 = Pt[3] + V[3], S21 = Pt[4] + V[4], S22 = Pt[5] + V[5];
   const bool in_ok = fin(r0) & fin(r1) & fin(r2) & fin(S00) & fin(S10) & fin(S11) & fin(S20) & fin(S21) & fin(S22);
   bool pd;
-  if (ZROW) {
+  // cylinders in FP32 through the Cholesky factor; planes, and the FP64 form
+  // (where each of the factor's three pivots would cost an IEEE square root
+  // and division against the cofactor form's one division), by cofactors
+  if constexpr (ZROW || !std::is_same<T, float>::value) {
     const T c00 = S11 * S22 - S21 * S21;
     const T c10 = S20 * S21 - S10 * S22;
     const T c11 = S00 * S22 - S20 * S20;
@@ -672,26 +676,47 @@ __device__ __forceinline__ uint32_t update_f32(T q[6], T Pt[21], const T m[3], c
     const T t1 = i10 * r0 + i11 * r1 + i21 * r2;
     const T t2 = i20 * r0 + i21 * r1 + i22 * r2;
     dchi = r0 * t0 + r1 * t1 + r2 * t2;
-    // row/column 2 of Pt vanish: K_i = Pt_i0 S^-1_0: + Pt_i1 S^-1_1:
-    T K0[6], K1[6];
+    if constexpr (ZROW) {
+      // row/column 2 of Pt vanish: K_i = Pt_i0 S^-1_0: + Pt_i1 S^-1_1:
+      T K0[6], K1[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-      if (i == 2) continue;
-      const T a = Pt[ix(i, 0)], c = Pt[ix(i, 1)];
-      K0[i] = a * i00 + c * i10;
-      K1[i] = a * i10 + c * i11;
+      for (int i = 0; i < 6; ++i) {
+        if (i == 2) continue;
+        const T a = Pt[ix(i, 0)], c = Pt[ix(i, 1)];
+        K0[i] = a * i00 + c * i10;
+        K1[i] = a * i10 + c * i11;
+      }
+      T Pn[21];
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+          Pn[ix(i, j)] = (i == 2 || j == 2) ? T(0) : Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)];
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+        if (i != 2) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1;
+#pragma unroll
+      for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
+    } else {
+      T K0[6], K1[6], K2[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) {
+        const T a = Pt[ix(i, 0)], c = Pt[ix(i, 1)], d = Pt[ix(i, 2)];
+        K0[i] = a * i00 + c * i10 + d * i20;
+        K1[i] = a * i10 + c * i11 + d * i21;
+        K2[i] = a * i20 + c * i21 + d * i22;
+      }
+      T Pn[21];
+#pragma unroll
+      for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+          Pn[ix(i, j)] = Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)] - K2[i] * Pt[ix(2, j)];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1 + Pt[ix(i, 2)] * t2;
+#pragma unroll
+      for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
     }
-    T Pn[21];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-      for (int j = 0; j <= i; ++j)
-        Pn[ix(i, j)] = (i == 2 || j == 2) ? T(0) : Pt[ix(i, j)] - K0[i] * Pt[ix(0, j)] - K1[i] * Pt[ix(1, j)];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-      if (i != 2) q[i] = q[i] + Pt[ix(i, 0)] * t0 + Pt[ix(i, 1)] * t1;
-#pragma unroll
-    for (int i = 0; i < 21; ++i) Pt[i] = Pn[i];
   } else {
     const Chol3<T> L = chol3(S00, S10, S11, S20, S21, S22);
     pd = L.pd;
