@@ -169,25 +169,72 @@ __device__ __forceinline__ float val(float x) { return x; }
 __device__ __forceinline__ double val(double x) { return x; }
 
 // The same helpers in FP64 (the full-FP64 form of the step).  The division is
-// exact IEEE division.  For |u| < 1/10 sin u, cos u, sinc u and G(u) come from
-// their Taylor series -- through u^10 (G through u^11), truncation below 1e-21
-// relative -- and beyond from the library's sin and cos and the closed forms,
-// where the cancellation in sin u - u cos u (about u^3/3) costs at most 7e-14
-// relative.  The direction's sin and cos are carried across layers as in FP32:
-// an update that moves an angle by |d| <= 1/8 rotates the pair by d (sin d
-// through d^13, cos d through d^14: truncation below 1e-24), a larger one
-// re-evaluates them; the carried pair drifts by about one ulp per layer.
+// exact IEEE division.  For |u| < 1/2, the range the FP32 helpers give to their
+// series too (a curved track's half turning angle between layers reaches a
+// few tenths), sin u, cos u, sinc u and G(u) come from their Taylor series --
+// sinc and cos through u^14, G through u^13: truncation below 5e-20, 1e-18 and
+// 1e-17 relative -- and beyond from the library's sin and cos and the closed
+// forms, where the cancellation in sin u - u cos u (about u^3/3) costs at most
+// 1e-15 relative.  A lane past 1/2 makes its whole wave run both branches, so
+// the series' range decides how often the library's sin and cos run at all.
+// The direction's sin and cos are carried across layers as in FP32: an update
+// that moves an angle by |d| <= 1/8 rotates the pair by d (sin d through d^11,
+// cos d through d^10: truncation below 1e-19), a larger one re-evaluates
+// them; the carried pair drifts by about one ulp per layer.
 __device__ __forceinline__ void sincos_t(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ double rcp_t(double x) { return 1.0 / x; }
 __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ double fmax_t(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ double fabs_t(double x) { return fabs(x); }
+
+// x y + c with the constant c read from a pair of scalar registers.  A series
+// coefficient is a wave-uniform 64-bit constant that a VOP3 FMA can take from
+// SGPRs (set by two scalar moves); the compiler's own choice is to copy each
+// into two VGPRs first, two more vector instructions per coefficient.
+__device__ __forceinline__ double fma_sc(double x, double y, double c) {
+  double r;
+  __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(y), "s"(c));
+  return r;
+}
+// The series of sinc u, cos u and (WANT_G) G(u)/u in x = u^2 by Horner's
+// rule, the chains advanced in lockstep: each FMA waits for its own chain's
+// last one only, so the chains' FMAs overlap (one chain alone would wait out
+// every FMA's latency).  The innermost term of each chain is a product and a
+// sum, in statements of their own (no contraction): an FMA reads at most one
+// scalar operand.
+template <bool WANT_G>
+__device__ __forceinline__ void trig_series64(double x, double& sinc, double& cosu, double& g_over_u) {
+  double a = x * (-1.0 / 1307674368000.0);  // sinc: through u^14
+  double c = x * (-1.0 / 87178291200.0);    // cos: through u^14
+  double g = x * (1.0 / 93405312000.0);     // G/u: through u^12
+  a = a + 1.0 / 6227020800.0;
+  c = c + 1.0 / 479001600.0;
+  if (WANT_G) g = g - 1.0 / 518918400.0;
+  a = fma_sc(x, a, -1.0 / 39916800.0);
+  c = fma_sc(x, c, -1.0 / 3628800.0);
+  if (WANT_G) g = fma_sc(x, g, 1.0 / 3991680.0);
+  a = fma_sc(x, a, 1.0 / 362880.0);
+  c = fma_sc(x, c, 1.0 / 40320.0);
+  if (WANT_G) g = fma_sc(x, g, -1.0 / 45360.0);
+  a = fma_sc(x, a, -1.0 / 5040.0);
+  c = fma_sc(x, c, -1.0 / 720.0);
+  if (WANT_G) g = fma_sc(x, g, 1.0 / 840.0);
+  a = fma_sc(x, a, 1.0 / 120.0);
+  c = fma_sc(x, c, 1.0 / 24.0);
+  if (WANT_G) g = fma_sc(x, g, -1.0 / 30.0);
+  a = fma_sc(x, a, -1.0 / 6.0);
+  c = fma_sc(x, c, -1.0 / 2.0);
+  if (WANT_G) g = fma_sc(x, g, 1.0 / 3.0);
+  sinc = __builtin_fma(x, a, 1.0);
+  cosu = __builtin_fma(x, c, 1.0);
+  if (WANT_G) g_over_u = g;
+}
+
 __device__ __forceinline__ void helix_sinc_t(double u, double& su, double& cu, double& sinc) {
-  const double u2 = u * u;
-  if (fabs(u) < 0.1) {
-    sinc = 1.0 + u2 * (-1.0 / 6.0 + u2 * (1.0 / 120.0 + u2 * (-1.0 / 5040.0 + u2 * (1.0 / 362880.0 + u2 * (-1.0 / 39916800.0)))));
+  if (fabs(u) < 0.5) {
+    double unused;
+    trig_series64<false>(u * u, sinc, cu, unused);
     su = u * sinc;
-    cu = 1.0 + u2 * (-1.0 / 2.0 + u2 * (1.0 / 24.0 + u2 * (-1.0 / 720.0 + u2 * (1.0 / 40320.0 + u2 * (-1.0 / 3628800.0)))));
   } else {
     rare_path();
     sincos(u, &su, &cu);
@@ -195,15 +242,16 @@ __device__ __forceinline__ void helix_sinc_t(double u, double& su, double& cu, d
   }
 }
 __device__ __forceinline__ void helix_trig_t(double u, double& su, double& cu, double& sinc, double& g) {
-  helix_sinc_t(u, su, cu, sinc);
-  const double u2 = u * u;
-  const double gs = u * (1.0 / 3.0 + u2 * (-1.0 / 30.0 + u2 * (1.0 / 840.0 + u2 * (-1.0 / 45360.0 + u2 * (1.0 / 3991680.0 +
-                                                                                       u2 * (-1.0 / 518918400.0))))));
-  if (fabs(u) < 0.1) {
-    g = gs;
+  if (fabs(u) < 0.5) {
+    double gu;
+    trig_series64<true>(u * u, sinc, cu, gu);
+    su = u * sinc;
+    g = u * gu;
   } else {
     rare_path();
-    g = (su - u * cu) / u2;
+    sincos(u, &su, &cu);
+    sinc = su / u;
+    g = (su - u * cu) / (u * u);
   }
 }
 __device__ __forceinline__ void dir_init(const double p[6], DirT<double>& d) {
@@ -212,11 +260,19 @@ __device__ __forceinline__ void dir_init(const double p[6], DirT<double>& d) {
 }
 __device__ __forceinline__ void rotate_by(double& s, double& c, double d, double angle) {
   if (fabs(d) <= 0.125) {
-    const double d2 = d * d;
-    const double sd =
-        d * (1.0 + d2 * (-1.0 / 6.0 + d2 * (1.0 / 120.0 + d2 * (-1.0 / 5040.0 + d2 * (1.0 / 362880.0 + d2 * (-1.0 / 39916800.0 + d2 * (1.0 / 6227020800.0)))))));
-    const double cd =
-        1.0 + d2 * (-0.5 + d2 * (1.0 / 24.0 + d2 * (-1.0 / 720.0 + d2 * (1.0 / 40320.0 + d2 * (-1.0 / 3628800.0 + d2 * (1.0 / 479001600.0 + d2 * (-1.0 / 87178291200.0)))))));
+    const double x = d * d;
+    double a = x * (-1.0 / 39916800.0);  // sin d / d: through d^10
+    double b = x * (-1.0 / 3628800.0);   // cos d: through d^10
+    a = a + 1.0 / 362880.0;
+    b = b + 1.0 / 40320.0;
+    a = fma_sc(x, a, -1.0 / 5040.0);
+    b = fma_sc(x, b, -1.0 / 720.0);
+    a = fma_sc(x, a, 1.0 / 120.0);
+    b = fma_sc(x, b, 1.0 / 24.0);
+    a = fma_sc(x, a, -1.0 / 6.0);
+    b = fma_sc(x, b, -1.0 / 2.0);
+    const double sd = d * __builtin_fma(x, a, 1.0);
+    const double cd = __builtin_fma(x, b, 1.0);
     const double sn = s * cd + c * sd;
     c = c * cd - s * sd;
     s = sn;
@@ -418,8 +474,20 @@ struct CylJac {
 // sp, cp: sin and cos of phi.
 __device__ __forceinline__ float search_tol(float) { return 1e-5f; }
 __device__ __forceinline__ double search_tol(double) { return 1e-9; }
-__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }  // 1 ulp; a start only
-__device__ __forceinline__ double sqrt_fast(double x) { return sqrt(x); }
+// The start's square root and the steps' reciprocals need not be correctly
+// rounded: the iteration corrects both.  In FP32 the hardware's 1-ulp square
+// root and reciprocal; in FP64 the hardware's square root (2^-23 relative, a
+// start only) and its reciprocal refined by two Newton-Raphson steps (from
+// 2^-23 relative to within an ulp or two), in 1 and 5 instructions where the
+// IEEE forms take 20 and 11.
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_fast(double x) { return __builtin_amdgcn_sqrt(x); }
+__device__ __forceinline__ float rcp_search(float x) { return rcp(x); }
+__device__ __forceinline__ double rcp_search(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 
 template <class T>
 __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T& cp, T rk, T b, bool& reachable) {
@@ -436,7 +504,7 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
   const T sq = sqrt_fast(fmax_t(beta * beta - a * g0, T(0)));
   const bool inward = g0 > T(0);
   const T den = inward ? sq - beta : beta + sq;
-  T s = (inward ? g0 : -g0) * rcp_t(den);
+  T s = (inward ? g0 : -g0) * rcp_search(den);
   if (!(den > T(0))) {
     rare_path();
     s = -beta + sqrt_fast(fmax_t(beta * beta - g0, T(0)));
@@ -458,7 +526,7 @@ __device__ __forceinline__ T cylinder_search(const T p[6], const T& sp, const T&
       const T c2 = cu * cu - su * su;
       const T s2 = 2.0f * su * cu;
       const T gp = 2.0f * (beta * c2 + gam * s2 + ch * cu);
-      const T ds = g * rcp_t(gp);
+      const T ds = g * rcp_search(gp);
       s = s - ds;
       run = !((fabs_t(ds) <= tol * fabs_t(s)) & (fabs_t(ds) <= T(0.1f) * fabs_t(prev)));
       prev = ds;
