@@ -283,6 +283,36 @@ def generate(name_or_workload, seed: int | None = None, n_events: int | None = N
     }
 
 
+def every_nth_layer(sample: dict, step: int) -> dict:
+    """The same tracks on every step-th layer of the table (layers 0, step,
+    2 step, ...) with the sample's own hits there; a track keeps the kept
+    layers it reached (nlay -> ceil(nlay / step))."""
+    keep = np.arange(0, sample["hit_pos"].shape[0], step)
+    out = dict(sample)
+    for k in ("hit_pos", "hit_cov"):
+        out[k] = sample[k][keep].copy()
+    for k in ("layer_z", "layer_r"):
+        out[k] = np.asarray(sample[k])[keep].copy()
+    out["nlay"] = ((np.asarray(sample["nlay"]) + step - 1) // step).astype(np.int32)
+    return out
+
+
+# Strongly curved tracks: low transverse momentum, so that the helix turns by
+# up to a radian or more between surfaces -- on the 5 cm plane spacing for
+# |q/pT| of 6-9 /GeV, on every third barrel layer (r = 5, 20, 35, ... cm) for
+# 4-8 /GeV (curling tracks reach only the first few cylinders).
+CURLED = {
+    "z": Workload("p2z_curled_4096", "z", 1, 4096, 20, seed_index=11, kappa_lo_z=6.0, kappa_hi_z=9.0),
+    "r": Workload("p2r_curled_4096", "r", 1, 4096, 20, seed_index=12, kappa_lo_r=4.0, kappa_hi_r=8.0),
+}
+
+
+def curled(geom: str) -> dict:
+    """The strongly curved sample for geometry "z" or "r" (see CURLED)."""
+    s = generate(CURLED[geom])
+    return s if geom == "z" else every_nth_layer(s, 3)
+
+
 def multi_hit(sample: dict, n_cand: int, spread: float = 3.0, seed: int = 0) -> dict:
     """Candidate hits for hit selection: on every layer each track gets its
     own hit plus n_cand - 1 decoys, at a random position in the list.  A

@@ -129,3 +129,16 @@ def assert_within(m: dict, tol: dict, what: str = ""):
     for k, v in tol.items():
         assert m[k] <= v, f"{what}: {k} = {m[k]:.3g} exceeds {v:.3g}  ({m})"
     assert m["zrow"] == 0.0 or m["zrow"] < 1e-30, f"{what}: plane z row not zero"
+
+
+def half_turning_angles(sample: dict, rec: dict) -> np.ndarray:
+    """|u| = |phi' - phi| / 2, the helix's half turning angle, of every update
+    the oracle's filter applied (rec: oracle.filter_record of the sample):
+    the argument of the helix functions between consecutive surfaces."""
+    done = rec["status"] >> 16
+    out = []
+    for k in range(rec["pred_p"].shape[0]):
+        prev = np.asarray(sample["par"]) if k == 0 else rec["filt_p"][k - 1]
+        act = done > k
+        out.append(np.abs(rec["pred_p"][k, act, 4] - prev[act, 4]) / 2)
+    return np.concatenate(out)

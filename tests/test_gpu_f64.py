@@ -1,20 +1,20 @@
 """The full-FP64 form (kf_propagate_update_z_f64 / _r_f64) against the FP64
 oracle: the same algorithm in the same precision, so the two differ only by
-operation order and by the kernel's short series for small helix angles.
+operation order and by the kernel's series for helix angles below 1/2.
 Gates (tests/parity.py metrics): see F64_TOL below."""
 import numpy as np
 import pytest
 
 import oracle as O
 from paper_2409_09228_amd import synth as S
-from parity import assert_within, metrics
+from parity import assert_within, half_turning_angles, metrics
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 # FP64 gates.  Largest differences measured over the tests below (both
-# geometries, all layouts, Joseph, 64 planes): parameters 5.5e-13 floored
+# geometries, all layouts, Joseph, 64 planes): parameters 4.1e-13 floored
 # relative and 3.0e-10 in sigma units, covariance 7.0e-13 correlation
 # units, chi-square 3.3e-11 relative.  Each gate is 30-200x that, and at
 # least five decades under the FP32 gates (1e-4 .. 5e-3), which a float
@@ -152,3 +152,21 @@ def test_full_size_sampled_f64(kf, name, geom):
     print(name, m)
     assert_within(m, F64_TOL, f"{name} f64 full size")
     np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
+
+
+@pytest.mark.parametrize("geom", ["z", "r"])
+def test_strongly_curved_tracks_f64(kf, geom):
+    """Helices turning by up to a radian or more between surfaces (the
+    strongly curved samples of synth.curled): updates with a half turning
+    angle |u| >= 1/2 take the library's sin and cos and the closed forms in
+    place of the series; the same gates as everywhere in FP64."""
+    g = 0 if geom == "z" else 1
+    s = S.curled(geom)
+    layers = s["layer_z"] if g == 0 else s["layer_r"]
+    rec = O.filter_record(g, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], layers, s["bz"], nlay=s["nlay"])
+    u = half_turning_angles(s, rec)
+    assert (u >= 0.5).mean() > 0.05 and u.max() > 0.8
+    got = _run(kf, s)
+    m = metrics(O.run_sample(s), got, g)
+    print(geom, m)
+    assert_within(m, F64_TOL, f"strongly curved {geom} f64")

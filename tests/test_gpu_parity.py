@@ -5,7 +5,7 @@ import pytest
 
 import oracle as O
 from paper_2409_09228_amd import synth as S
-from parity import TOL_F32, TOL_PRECISION, assert_two_sided, assert_within, calibrated, metrics
+from parity import TOL_F32, TOL_PRECISION, assert_two_sided, assert_within, calibrated, half_turning_angles, metrics
 
 pytestmark = pytest.mark.gpu
 
@@ -453,3 +453,26 @@ def test_precision_form_full_size_sampled(kf, name, geom):
     print(name, m)
     assert_within(m, TOL_PRECISION, f"{name} flags=3 full size")
     np.testing.assert_array_equal(got[3] >> 16, s["nlay"])
+
+
+@pytest.mark.parametrize("geom", ["z", "r"])
+def test_strongly_curved_tracks(kf, geom):
+    """Helices turning by up to a radian or more between surfaces (planes:
+    |q/pT| 6-9 /GeV on the 20 planes; cylinders: 4-8 /GeV on every third
+    layer): some updates have a half turning angle |u| >= 1/2, past the helix
+    functions' series, and take the reduced sin/cos and the closed forms.
+    Statuses as in the oracle, states within the calibrated FP32 gates."""
+    g = 0 if geom == "z" else 1
+    s = S.curled(geom)
+    layers = s["layer_z"] if g == 0 else s["layer_r"]
+    rec = O.filter_record(g, s["par"], s["cov"], s["hit_pos"], s["hit_cov"], layers, s["bz"], nlay=s["nlay"])
+    u = half_turning_angles(s, rec)
+    print(geom, "updates", len(u), "with |u| >= 1/2:", int((u >= 0.5).sum()), "max |u|", float(u.max()))
+    assert (u >= 0.5).mean() > 0.05 and u.max() > 0.8
+    got = _gpu_run(kf, s)
+    ref = _oracle(s)
+    np.testing.assert_array_equal(got[3], ref[3])
+    m = metrics(ref, got, g)
+    f32 = metrics(ref, O.run_sample(s, precision="f32"), g)
+    print(m, f32)
+    assert_within(m, calibrated(TOL_F32, f32), f"strongly curved {geom}")

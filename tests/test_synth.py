@@ -76,3 +76,27 @@ def test_host_layout_roundtrip():
     y = rng.normal(size=(n, E))
     for lay in (K.SOA, K.AOS, K.aosoa(32)):
         np.testing.assert_array_equal(K.from_layout_np(K.to_layout_np(y, lay), E, 1, n, lay), y)
+
+
+def test_every_nth_layer_and_curled_samples():
+    """every_nth_layer keeps layers 0, step, 2 step, ... with their own hits
+    and ceil(nlay / step) layers per track; the strongly curved samples draw
+    |q/pT| in their ranges and keep their hits on the surfaces."""
+    s = S.subset(S.generate("p2r_100x9600", n_events=1), np.arange(500))
+    t = S.every_nth_layer(s, 3)
+    assert np.array_equal(t["layer_r"], s["layer_r"][::3])
+    assert np.array_equal(t["hit_pos"], s["hit_pos"][::3])
+    assert np.array_equal(t["nlay"], -(-s["nlay"] // 3))
+    for geom, lo, hi in (("z", 6.0, 9.0), ("r", 4.0, 8.0)):
+        c = S.curled(geom)
+        k = np.abs(c["truth"][:, 3])
+        assert k.min() >= lo and k.max() <= hi
+        L = c["hit_pos"].shape[0]
+        used = np.arange(L)[:, None] < c["nlay"][None, :]
+        if geom == "z":  # smeared along z by 0.01 cm
+            dz = c["hit_pos"][..., 2] - c["layer_z"][:, None]
+            assert np.abs(dz[used]).max() < 0.1
+        else:  # on the cylinders
+            r = np.hypot(c["hit_pos"][..., 0], c["hit_pos"][..., 1])
+            np.testing.assert_allclose(r[used], np.broadcast_to(c["layer_r"][:, None], r.shape)[used], rtol=1e-12)
+            assert np.array_equal(c["layer_r"], 5.0 + 15.0 * np.arange(7))
