@@ -231,12 +231,12 @@ hipError_t launch_step(int geom, int prec, int block, int tpt, const StepArgs& a
 
 // ---------------------------------------------------------------- FP64 form
 // The same step in FP64 end to end (arrays, field constant, layer table and
-// arithmetic).  Planes fetch their hits one layer ahead into registers.  The
-// cylinder step's double state needs more than the 256 VGPRs that leave room
-// for two waves per SIMD: it loads each layer's hit when the layer comes and
-// is compiled for two waves per SIMD regardless, spilling a little (one wave
-// per SIMD without spills: 0.91 ms per launch on the barrel sample; two waves
-// with the prefetch: 0.74 ms; two waves, hits loaded on use: 0.71 ms).
+// arithmetic).  Planes fetch their hits one layer ahead into registers (two
+// layers ahead was slower: 0.383 against 0.375 ms per launch on the plane
+// sample).  The cylinder step's double state fills the 256 VGPRs that leave
+// room for two waves per SIMD (253, no spills), so it loads each layer's hit
+// at the top of that layer, where the search covers the latency; with the
+// one-layer prefetch it would spill.
 template <int GEOM, int PREC, int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
 kf_step_kernel_f64(const StepArgsT<double> a) {
