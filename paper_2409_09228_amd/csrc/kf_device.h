@@ -187,10 +187,12 @@ __device__ __forceinline__ double sqrt_t(double x) { return sqrt(x); }
 __device__ __forceinline__ double fmax_t(double a, double b) { return fmax(a, b); }
 __device__ __forceinline__ double fabs_t(double x) { return fabs(x); }
 
-// x y + c with the constant c read from a pair of scalar registers.  A series
-// coefficient is a wave-uniform 64-bit constant that a VOP3 FMA can take from
-// SGPRs (set by two scalar moves); the compiler's own choice is to copy each
-// into two VGPRs first, two more vector instructions per coefficient.
+// x y + c with c read from a pair of scalar registers.  c must hold the same
+// value in every lane -- every caller passes a literal series coefficient --
+// since a scalar operand is one value for the whole wave.  A VOP3 FMA takes
+// such a 64-bit constant from SGPRs (set by two scalar moves); the compiler's
+// own choice is to copy it into two VGPRs first, two more vector instructions
+// per coefficient.
 __device__ __forceinline__ double fma_sc(double x, double y, double c) {
   double r;
   __asm__("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(y), "s"(c));
